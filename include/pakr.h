@@ -1,0 +1,253 @@
+/*
+ * pakr.h -- C ABI of the MI355X (gfx950) PAKR planner library (libpakr.so).
+ *
+ * PAKR is the parallel asymptotically optimal kinodynamic RRT of
+ * "Fast Asymptotically Optimal Kinodynamic Planning via Vectorization"
+ * (Gao, Lu, Kingston).  The library runs Alg. 1 of the paper on one GPU:
+ * an AO-x outer loop (restart with a tighter cost bound c_best after every
+ * solution) around a batched kinodynamic RRT whose inner iteration samples
+ * K = B/A target states, finds each target's nearest tree node, samples A
+ * controls per selected parent, rolls all B candidates out with RK4 for T
+ * steps of dt with the control held, checks every sub-step for validity,
+ * prunes candidates whose cost-to-come plus heuristic is not below c_best,
+ * and appends the survivors to the tree in candidate order.
+ *
+ * The problem statement (Sec. III) fixes the inputs: dynamics f, start
+ * x_init in X_free, goal region X_goal, cost J, control space U; Alg. 1 adds
+ * the batch size B and branching factor A; Sec. IV-A adds the step dt, the
+ * step count T and the static tree capacity N.
+ *
+ * Conventions
+ *  - All entry points return int: PAKR_OK (0) or a negative pakr_error.
+ *    No C++ exception crosses the ABI.  pakr_last_error() gives a message.
+ *  - Host pointers (marked "host") are read during the call only; the caller
+ *    keeps ownership.  Device pointers (marked "device") must stay valid for
+ *    as long as the plan uses them.
+ *  - `stream` is a hipStream_t passed as void*.  Calls marked "async" only
+ *    enqueue work on that stream; calls marked "syncs" wait for it.
+ *  - Real-valued inputs are float32: the planner is defined on those exact
+ *    values.  The device path computes in float32.
+ *  - Random draws use Philox4x32-10 (Salmon et al., SC'11) with key
+ *    (low 32 bits of seed, query_id) and counter (index, iteration in round,
+ *    round, tag << 16 | sub): tag 0 draws targets (index = target k, sub =
+ *    block of four state dimensions), tag 1 draws controls (index = parent
+ *    query k, sub = branch a).  A u32 word x maps to [lo, hi] as
+ *    lo + (hi - lo) * ((x >> 8) * 2^-24) with one float32 rounding per
+ *    operation and no fused multiply-add.
+ */
+#ifndef PAKR_H
+#define PAKR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PAKR_MAX_D 12          /* largest state dimension (quadrotor) */
+#define PAKR_MAX_M 4           /* largest control dimension */
+#define PAKR_MAX_OBSTACLES 1024 /* boxes + spheres per scene (held in LDS) */
+#define PAKR_MAX_B 65536       /* rollouts per iteration */
+
+/* Systems (Sec. V-A names the double integrator and the quadcopter; the
+ * second-order car is a unicycle-2-like model with steering). */
+enum pakr_system_id {
+  PAKR_DI2 = 0,  /* 2D double integrator: x=(px,py,vx,vy), u=(ax,ay)        */
+  PAKR_DI3 = 1,  /* 3D double integrator: x=(p, v) in R^6, u=a in R^3       */
+  PAKR_CAR = 2,  /* car: x=(px,py,theta,v,phi), u=(accel, steering rate)     */
+  PAKR_QUAD = 3  /* quadrotor: x=(p, roll,pitch,yaw, body vel, body rates),
+                    u=(thrust, tau_x, tau_y, tau_z)                          */
+};
+
+/* Cost J (Sec. III): trajectory duration or path length of the positions. */
+enum pakr_cost_kind { PAKR_COST_DURATION = 0, PAKR_COST_PATH_LENGTH = 1 };
+
+/* Heuristic h of the prune g + h < c_best (Alg. 1).  ADMISSIBLE measures the
+ * position distance to the goal ball and divides it by h_speed for a duration
+ * cost; PAPER_LITERAL is the Euclidean position distance to the goal centre;
+ * NONE is 0. */
+enum pakr_heuristic_kind { PAKR_H_ADMISSIBLE = 0, PAKR_H_PAPER_LITERAL = 1, PAKR_H_NONE = 2 };
+
+enum pakr_error {
+  PAKR_OK = 0,
+  PAKR_E_INVALID_ARG = -1,          /* malformed sizes, pointers or parameters   */
+  PAKR_E_START_INVALID = -2,        /* x_init outside X_free or its limits       */
+  PAKR_E_GOAL_INVALID = -3,         /* goal centre outside the workspace, r <= 0 */
+  PAKR_E_WORKSPACE_TOO_SMALL = -4,  /* ws_bytes < pakr_workspace_size()          */
+  PAKR_E_HIP = -5,                  /* a HIP runtime call failed                 */
+  PAKR_E_NO_SOLUTION = -6,          /* no solution found yet                     */
+  PAKR_E_BUFFER_TOO_SMALL = -7,     /* caller buffer cannot hold the result      */
+  PAKR_E_DEVICE = -8                /* device-side failure (grid barrier timeout) */
+};
+
+/* Status bits reported in pakr_stats.status (why the last call stopped). */
+enum pakr_status_bits {
+  PAKR_S_SOLVED = 1,          /* at least one solution exists               */
+  PAKR_S_BUDGET_EXPIRED = 2,  /* the device-clock budget ran out            */
+  PAKR_S_ROUNDS_DONE = 4,     /* max_rounds rounds completed                */
+  PAKR_S_ITERS_DONE = 8,      /* the iteration budget of the call was used  */
+  PAKR_S_TREE_FULL = 16,      /* some round ended with a full tree          */
+  PAKR_S_ITER_CAP = 32,       /* some round hit max_iters_per_round         */
+  PAKR_S_DEVICE_ERROR = 64    /* a grid barrier timed out (see PAKR_E_DEVICE) */
+};
+
+/* Dynamics and limits of one system.  Every field is required; the Python
+ * package fills it from a per-system table. */
+typedef struct pakr_system {
+  int id;                          /* pakr_system_id                                  */
+  int d, m;                        /* state / control dimension, must match id        */
+  float dyn[8];                    /* CAR: [0]=wheelbase; QUAD: mass, g, Ixx, Iyy, Izz */
+  float sample_lo[PAKR_MAX_D];     /* SampleStates box per state dimension            */
+  float sample_hi[PAKR_MAX_D];
+  float u_lo[PAKR_MAX_M];          /* control box U                                   */
+  float u_hi[PAKR_MAX_M];
+  float lim_lo[PAKR_MAX_D];        /* state limits, valid iff lim_lo <= x <= lim_hi;   */
+  float lim_hi[PAKR_MAX_D];        /*   use -/+INFINITY for "no limit"                */
+  float vnorm_max;                 /* |velocity| <= vnorm_max (double integrators); 0 = none */
+} pakr_system;
+
+/* Workspace and obstacles (host arrays, copied by pakr_plan_init).  A point
+ * robot at the first npos state coordinates must lie in the closed box
+ * [ws_lo, ws_hi] and outside every closed obstacle. */
+typedef struct pakr_scene {
+  int npos;                        /* 2 (DI2, CAR) or 3 (DI3, QUAD)                    */
+  float ws_lo[3], ws_hi[3];
+  int n_box;                       /* axis-aligned boxes                              */
+  const float* box_c;              /* host [n_box][npos] centres                      */
+  const float* box_h;              /* host [n_box][npos] half extents (> 0)           */
+  int n_sphere;                    /* spheres (discs when npos = 2)                   */
+  const float* sph_c;              /* host [n_sphere][npos] centres                   */
+  const float* sph_r;              /* host [n_sphere] radii (> 0)                     */
+} pakr_scene;
+
+/* Goal region: closed ball of `radius` around `center` in position space. */
+typedef struct pakr_goal {
+  float center[3];
+  float radius;
+} pakr_goal;
+
+typedef struct pakr_params {
+  int B;                           /* rollouts per iteration, 1..PAKR_MAX_B, B % A == 0 */
+  int A;                           /* branching factor, controls per selected parent    */
+  int T;                           /* RK4 steps per edge (>= 1)                          */
+  float dt;                        /* step length (> 0)                                 */
+  int n_cap;                       /* tree capacity N (root included), > B              */
+  int cost_kind;                   /* pakr_cost_kind                                    */
+  int heuristic_kind;              /* pakr_heuristic_kind                               */
+  float h_speed;                   /* speed bound used by PAKR_H_ADMISSIBLE + duration  */
+  double cost_bound;               /* initial c_best, +INFINITY for none (> 0)          */
+  uint64_t seed;                   /* Philox key word 0 = low 32 bits                   */
+  uint32_t query_id;               /* Philox key word 1                                 */
+  int max_iters_per_round;         /* a round with no solution ends after this many     */
+  int grid;                        /* workgroups of the persistent launch, 0 = auto     */
+  int max_path_edges;              /* capacity of the stored best path, 0 = 4096        */
+} pakr_params;
+
+typedef struct pakr_stats {
+  int n_nodes;                     /* nodes in the current round's tree                 */
+  int round;                       /* current AO-x round (0-based)                      */
+  int iter;                        /* iteration within the current round                */
+  int status;                      /* pakr_status_bits of the last call                 */
+  int n_solutions;                 /* solutions found since pakr_plan_init              */
+  int grid;                        /* workgroups used by the persistent launch          */
+  long long total_iters;           /* inner iterations since pakr_plan_init             */
+  long long expansions;            /* candidates rolled out (B per iteration)           */
+  long long insertions;            /* nodes inserted                                    */
+  long long nn_pairs;              /* (query, node) distance evaluations                */
+  double c_best;                   /* current bound (+INFINITY before the first solution) */
+  double call_ms;                  /* device-clock duration of the last call            */
+  double t_first_ms;               /* device time of the first solution of the last call, -1 */
+  double t_last_ms;                /* device time of its last solution, -1              */
+  int call_iters;                  /* iterations run by the last call                   */
+  int call_rounds;                 /* rounds completed by the last call                 */
+  int call_solutions;              /* solutions found by the last call                  */
+  int reserved;
+} pakr_stats;
+
+typedef struct pakr_solution {
+  int round, iter;                 /* when it was found                                 */
+  int node;                        /* tree slot of the goal node                        */
+  int n_nodes;                     /* tree size at that iteration                       */
+  long long total_iter;            /* global iteration index                            */
+  double cost;                     /* its cost, the new c_best                          */
+  double t_ms;                     /* device time since the start of the call that found it */
+} pakr_solution;
+
+typedef struct pakr_plan pakr_plan;
+
+/* Device bytes needed by a plan (tree, work buffers, trace-free).  Pure host
+ * function; returns 0 for invalid sizes. */
+size_t pakr_workspace_size(const pakr_system* sys, const pakr_params* params,
+                           const pakr_scene* scene);
+
+/* Validate the query (Sec. III: x_init in X_free, goal region in the
+ * workspace; Alg. 1: B/A integral), copy the scene to the device and write
+ * the root (x_init, no action, cost 0).  `d_workspace` (device, caller-owned,
+ * >= pakr_workspace_size bytes, 256-byte aligned) holds every device buffer of
+ * the plan; if NULL the library allocates and owns it.  Enqueues on `stream`;
+ * the host arrays are copied before return.  *out is freed with
+ * pakr_plan_destroy. */
+int pakr_plan_init(const pakr_system* sys, const pakr_scene* scene, const float* x_init,
+                   const pakr_goal* goal, const pakr_params* params, void* d_workspace,
+                   size_t ws_bytes, void* stream, pakr_plan** out);
+
+/* Free the plan (and the workspace if the library allocated it).  Syncs. */
+void pakr_plan_destroy(pakr_plan* plan);
+
+/* Bytes of a trace buffer holding n_iters iteration records (layout below). */
+size_t pakr_trace_bytes(const pakr_plan* plan, int n_iters);
+
+/* Run exactly n_iters inner iterations of Alg. 1 (rounds end and restart as
+ * the algorithm says), recording each into `d_trace` (device, nullable,
+ * >= pakr_trace_bytes(plan, n_iters)).  Async.
+ *
+ * Trace record i, int32 words at d_trace + i * pakr_trace_bytes(plan, 1):
+ *   [0] round [1] iter [2] n0 (tree size at start) [3] n1 (at end)
+ *   [4] goal candidate j or -1 [5] its slot or -1 [6] end reason
+ *       (0 none, 1 goal, 2 tree full, 3 iteration cap)
+ *   [7] c_best before (float bits) [8] c_best after (float bits)
+ *   [9] survivors [10..15] reserved
+ *   then targets K*d floats, parents K ints, controls B*m floats,
+ *   final states B*d floats, costs B floats, flags B ints
+ *   (1 valid, 2 under the bound, 4 kept, 8 final state in the goal), and
+ *   slots B ints (tree slot, or -1 if not inserted). */
+int pakr_expand(pakr_plan* plan, int n_iters, void* d_trace, size_t trace_bytes);
+
+/* Run the AO-x loop on the device until the device-clock budget (ms, > 0)
+ * runs out, `max_rounds` (> 0) rounds complete, or `max_iters` (> 0)
+ * iterations have run -- whichever comes first; a value <= 0 disables that
+ * limit, and at least one must be set.  Async. */
+int pakr_replan(pakr_plan* plan, double budget_ms, int max_rounds, long long max_iters);
+
+/* Counters and timings (syncs). */
+int pakr_status(pakr_plan* plan, pakr_stats* out);
+
+/* Solutions found so far (syncs).  Writes min(cap, count) records, *n_total
+ * receives the count. */
+int pakr_solutions(pakr_plan* plan, pakr_solution* out, int cap, int* n_total);
+
+/* ExtractPath (Alg. 1): the best trajectory found, root first (syncs).
+ * states: host [(n_edges + 1)][d]; actions: host [n_edges][m], the control
+ * held on each edge.  PAKR_E_NO_SOLUTION with *n_edges = 0 if none yet;
+ * PAKR_E_BUFFER_TOO_SMALL with *n_edges set if cap_edges is too small. */
+int pakr_extract_path(pakr_plan* plan, float* states, float* actions, int cap_edges,
+                      int* n_edges, double* cost);
+
+/* Copy the current round's tree to host arrays, node-major (syncs):
+ * states [n][d], actions [n][m], parents [n] (root -1), costs [n]; any may be
+ * NULL.  At most n_max nodes; *n receives the tree size. */
+int pakr_copy_tree(pakr_plan* plan, float* states, float* actions, int* parents, float* costs,
+                   int n_max, int* n);
+
+/* Message for the last error of `plan` (or of the last failed
+ * pakr_plan_init when plan is NULL).  Valid until the next call. */
+const char* pakr_last_error(const pakr_plan* plan);
+
+/* Static name of an error code. */
+const char* pakr_error_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PAKR_H */

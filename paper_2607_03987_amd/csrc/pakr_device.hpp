@@ -1,0 +1,272 @@
+// Device-side building blocks of the PAKR planner for gfx950: the problem
+// record, Philox draws, system dynamics, RK4 and the per-state validity test.
+// float32 throughout.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/pakr.h"
+
+namespace pakr {
+
+constexpr int NT = 256;          // threads per workgroup (four wave64s)
+constexpr int WAVE = 64;
+constexpr int MAX_SOLUTIONS = 1024;
+
+enum : int { F_VALID = 1, F_PRUNE_OK = 2, F_KEEP = 4, F_GOAL = 8 };
+enum : int { END_NONE = 0, END_GOAL = 1, END_TREE_FULL = 2, END_ITER_CAP = 3 };
+constexpr int TRACE_HDR_WORDS = 16;
+
+// Everything a kernel needs to know about one query; passed by value.
+struct DevProblem {
+  int system, d, m, npos;
+  int B, A, K, T;
+  int n_cap, cost_kind, h_kind, max_iters_per_round;
+  int n_box, n_sph, G, G_roll;
+  int max_path_edges, obs_floats;
+  uint32_t key0, key1;
+  float dt, h_speed, c0, vnorm_max;
+  float goal_r, goal_r2, edge_duration, pad0;
+  float dyn[8];
+  float sample_lo[PAKR_MAX_D], sample_hi[PAKR_MAX_D];
+  float lim_lo[PAKR_MAX_D], lim_hi[PAKR_MAX_D];
+  float u_lo[PAKR_MAX_M], u_hi[PAKR_MAX_M];
+  float ws_lo[3], ws_hi[3], goal_c[3], pad1[3];
+};
+
+// Loop state and per-call results; lives at the start of the workspace.
+struct DevHeader {
+  int n, round, iter, n_solutions;           // persistent loop state
+  float c_best;
+  int status;                                // pakr_status_bits of the last call
+  uint32_t bar_gen;                          // grid-barrier generation counter
+  int err;                                   // nonzero after a barrier timeout
+  unsigned long long total_iters, expansions, insertions, nn_pairs;
+  long long t_start, t_end, t_first, t_last; // device wall-clock ticks of the last call
+  int call_iters, call_rounds, call_solutions, path_truncated;
+  int best_edges, best_node, pad0, pad1;
+  float best_cost, pad2, pad3, pad4;
+  uint32_t release;                          // barrier release word
+  int stop[2];                               // per-iteration stop decision (parity)
+  int pad5;
+};
+
+struct DevSolution {
+  int round, iter, node, n_nodes;
+  long long total_iter;
+  float cost;
+  int pad;
+  long long t;
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                              uint32_t k0, uint32_t k1, uint32_t out[4]) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+// u32 -> [lo, hi]: top 24 bits scaled exactly to [0,1), then lo + (hi-lo)*u
+// with one float32 rounding per operation (no contraction into an FMA).
+__device__ __forceinline__ float draw_range(uint32_t x, float lo, float hi) {
+#pragma clang fp contract(off)
+  const float u = (float)(x >> 8) * 5.9604644775390625e-08f;
+  const float w = hi - lo;
+  const float p = w * u;
+  return lo + p;
+}
+
+enum : uint32_t { TAG_STATE = 0u, TAG_CONTROL = 1u };
+
+// SampleStates: target k of iteration `it` of round `rd`.
+template <int D>
+__device__ __forceinline__ void sample_state(const DevProblem& P, uint32_t k, uint32_t it,
+                                             uint32_t rd, float* q) {
+#pragma unroll
+  for (int blk = 0; blk * 4 < D; ++blk) {
+    uint32_t r[4];
+    philox4x32_10(k, it, rd, (TAG_STATE << 16) | (uint32_t)blk, P.key0, P.key1, r);
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const int c = blk * 4 + w;
+      if (c < D) q[c] = draw_range(r[w], P.sample_lo[c], P.sample_hi[c]);
+    }
+  }
+}
+
+// SampleControls: branch a of parent query k.
+template <int M>
+__device__ __forceinline__ void sample_control(const DevProblem& P, uint32_t k, uint32_t a,
+                                               uint32_t it, uint32_t rd, float* u) {
+  uint32_t r[4];
+  philox4x32_10(k, it, rd, (TAG_CONTROL << 16) | a, P.key0, P.key1, r);
+#pragma unroll
+  for (int c = 0; c < M; ++c) u[c] = draw_range(r[c], P.u_lo[c], P.u_hi[c]);
+}
+
+// ---------------------------------------------------------------------------
+// Systems.  Sizes are compile-time so every state lives in registers.
+// ---------------------------------------------------------------------------
+template <int SYS> struct Sys;
+template <> struct Sys<PAKR_DI2> { static constexpr int D = 4, M = 2, P = 2; };
+template <> struct Sys<PAKR_DI3> { static constexpr int D = 6, M = 3, P = 3; };
+template <> struct Sys<PAKR_CAR> { static constexpr int D = 5, M = 2, P = 2; };
+template <> struct Sys<PAKR_QUAD> { static constexpr int D = 12, M = 4, P = 3; };
+
+// x' = f(x, u), Eq. (1).
+template <int SYS>
+__device__ __forceinline__ void dynamics(const DevProblem& P, const float* x, const float* u,
+                                         float* xd) {
+  if constexpr (SYS == PAKR_DI2 || SYS == PAKR_DI3) {
+    constexpr int Dp = Sys<SYS>::P;
+#pragma unroll
+    for (int a = 0; a < Dp; ++a) {
+      xd[a] = x[Dp + a];
+      xd[Dp + a] = u[a];
+    }
+  } else if constexpr (SYS == PAKR_CAR) {
+    float s, c;
+    sincosf(x[2], &s, &c);
+    const float v = x[3];
+    xd[0] = v * c;
+    xd[1] = v * s;
+    xd[2] = v * tanf(x[4]) * (1.0f / P.dyn[0]);
+    xd[3] = u[0];
+    xd[4] = u[1];
+  } else {
+    // quadrotor, Z-Y-X Euler angles; body-frame velocity (ub,vb,wb), rates (p,q,r)
+    const float inv_m = 1.0f / P.dyn[0], g = P.dyn[1];
+    const float Ix = P.dyn[2], Iy = P.dyn[3], Iz = P.dyn[4];
+    float sph, cph, sth, cth, sps, cps;
+    sincosf(x[3], &sph, &cph);
+    sincosf(x[4], &sth, &cth);
+    sincosf(x[5], &sps, &cps);
+    const float ub = x[6], vb = x[7], wb = x[8];
+    const float p = x[9], q = x[10], r = x[11];
+    // rotation body -> world, R = Rz(yaw) Ry(pitch) Rx(roll)
+    const float r00 = cps * cth, r01 = cps * sth * sph - sps * cph, r02 = cps * sth * cph + sps * sph;
+    const float r10 = sps * cth, r11 = sps * sth * sph + cps * cph, r12 = sps * sth * cph - cps * sph;
+    const float r20 = -sth, r21 = cth * sph, r22 = cth * cph;
+    xd[0] = r00 * ub + r01 * vb + r02 * wb;
+    xd[1] = r10 * ub + r11 * vb + r12 * wb;
+    xd[2] = r20 * ub + r21 * vb + r22 * wb;
+    const float inv_cth = 1.0f / cth;
+    const float qs_rc = q * sph + r * cph;
+    xd[3] = p + qs_rc * sth * inv_cth;
+    xd[4] = q * cph - r * sph;
+    xd[5] = qs_rc * inv_cth;
+    // v_b' = -w x v_b + R^T (0,0,-g) + (0,0,thrust/m)
+    xd[6] = -(q * wb - r * vb) - g * r20;
+    xd[7] = -(r * ub - p * wb) - g * r21;
+    xd[8] = -(p * vb - q * ub) - g * r22 + u[0] * inv_m;
+    // w' = I^-1 (tau - w x I w)
+    xd[9] = (u[1] - (Iz - Iy) * q * r) / Ix;
+    xd[10] = (u[2] - (Ix - Iz) * r * p) / Iy;
+    xd[11] = (u[3] - (Iy - Ix) * p * q) / Iz;
+  }
+}
+
+// One classical RK4 step with the control held (Sec. IV-A).
+template <int SYS>
+__device__ __forceinline__ void rk4_step(const DevProblem& P, float* x, const float* u, float h) {
+  constexpr int D = Sys<SYS>::D;
+  float k1[D], k2[D], k3[D], k4[D], t[D];
+  const float hh = 0.5f * h;
+  dynamics<SYS>(P, x, u, k1);
+#pragma unroll
+  for (int i = 0; i < D; ++i) t[i] = x[i] + hh * k1[i];
+  dynamics<SYS>(P, t, u, k2);
+#pragma unroll
+  for (int i = 0; i < D; ++i) t[i] = x[i] + hh * k2[i];
+  dynamics<SYS>(P, t, u, k3);
+#pragma unroll
+  for (int i = 0; i < D; ++i) t[i] = x[i] + h * k3[i];
+  dynamics<SYS>(P, t, u, k4);
+  const float h6 = h * (1.0f / 6.0f);
+#pragma unroll
+  for (int i = 0; i < D; ++i) x[i] = x[i] + h6 * (k1[i] + 2.0f * (k2[i] + k3[i]) + k4[i]);
+}
+
+// Validity of one state: closed workspace, state limits, outside every closed
+// obstacle.  Obstacles sit in LDS: boxes first as (c[NP], h[NP]) records,
+// then spheres as (c[NP], r^2).  NaN compares false and so is invalid.
+template <int SYS>
+__device__ __forceinline__ bool state_ok(const DevProblem& P, const float* x, const float* s_obs) {
+  constexpr int D = Sys<SYS>::D, NP = Sys<SYS>::P;
+  bool ok = true;
+#pragma unroll
+  for (int c = 0; c < NP; ++c) ok = ok && (x[c] >= P.ws_lo[c]) && (x[c] <= P.ws_hi[c]);
+#pragma unroll
+  for (int i = NP; i < D; ++i) ok = ok && (x[i] >= P.lim_lo[i]) && (x[i] <= P.lim_hi[i]);
+  if constexpr (SYS == PAKR_DI2 || SYS == PAKR_DI3) {
+    if (P.vnorm_max > 0.0f) {
+      float s2 = 0.0f;
+#pragma unroll
+      for (int c = 0; c < NP; ++c) s2 += x[NP + c] * x[NP + c];
+      ok = ok && (s2 <= P.vnorm_max * P.vnorm_max);
+    }
+  }
+  bool hit = false;
+  const int nb = P.n_box;
+  for (int b = 0; b < nb; ++b) {
+    const float* o = s_obs + b * (2 * NP);
+    bool inside = true;
+#pragma unroll
+    for (int c = 0; c < NP; ++c) inside = inside && (fabsf(x[c] - o[c]) <= o[NP + c]);
+    hit = hit || inside;
+  }
+  const float* sp = s_obs + nb * (2 * NP);
+  const int ns = P.n_sph;
+  for (int s = 0; s < ns; ++s) {
+    const float* o = sp + s * (NP + 1);
+    float d2 = 0.0f;
+#pragma unroll
+    for (int c = 0; c < NP; ++c) {
+      const float e = x[c] - o[c];
+      d2 += e * e;
+    }
+    hit = hit || (d2 <= o[NP]);
+  }
+  return ok && !hit;
+}
+
+template <int SYS>
+__device__ __forceinline__ float goal_dist2(const DevProblem& P, const float* x) {
+  constexpr int NP = Sys<SYS>::P;
+  float s2 = 0.0f;
+#pragma unroll
+  for (int c = 0; c < NP; ++c) {
+    const float e = x[c] - P.goal_c[c];
+    s2 += e * e;
+  }
+  return s2;
+}
+
+// h(x) of the prune test.
+template <int SYS>
+__device__ __forceinline__ float heuristic(const DevProblem& P, float dist) {
+  if (P.h_kind == PAKR_H_NONE) return 0.0f;
+  if (P.h_kind == PAKR_H_PAPER_LITERAL) return dist;
+  float gap = fmaxf(dist - P.goal_r, 0.0f);
+  if (P.cost_kind == PAKR_COST_DURATION) gap = gap / P.h_speed;
+  return gap;
+}
+
+}  // namespace pakr

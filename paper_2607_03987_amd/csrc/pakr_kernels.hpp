@@ -1,0 +1,589 @@
+// The PAKR planner kernel for gfx950.
+//
+// One cooperative launch of G workgroups runs the AO-x loop of Alg. 1 on the
+// device with no host round-trip.  Each inner iteration has three phases
+// separated by two grid barriers:
+//
+//   1. SampleStates + NearestNeighbor.  Every workgroup draws all K targets
+//      (Philox, registers) and scans the tree tiles it owns -- tile t (256
+//      nodes) belongs to workgroup t mod G -- staging each tile through LDS and
+//      keeping a per-target (distance, index) minimum.  The partial minima go
+//      to HBM as packed u64 keys [G][K].
+//   2. SampleControls + Propagate + CollisionFree + prune.  Workgroup w < G_roll
+//      owns candidates j in [256w, 256w+256): it reduces the partial minima of
+//      its parents, rolls each candidate out with RK4 (one lane per candidate,
+//      obstacles in LDS), and compacts the survivors in candidate order into a
+//      staging area with a wave ballot + prefix count.
+//   3. Insert + bookkeeping.  All workgroups read the survivor counts, take an
+//      exclusive prefix, and copy the survivors that land in their own tiles
+//      from staging into the tree (so the next phase 1 reads only slots its
+//      workgroup wrote itself, and needs no extra barrier).  The goal test, the
+//      bound update and the round end are computed identically by every
+//      workgroup; workgroup 0 records solutions and walks the parent chain.
+//
+// Survivor slots are n + (number of survivors before j): insertion order is
+// deterministic and equal to the sequential order of Alg. 1.
+#pragma once
+
+#include <limits.h>
+
+#include "pakr_device.hpp"
+
+namespace pakr {
+
+struct KArgs {
+  DevProblem P;
+  DevHeader* hdr;
+  uint32_t* bar_flags;              // [G] arrival generation per workgroup
+  DevSolution* sols;                // [MAX_SOLUTIONS]
+  float* path_states;               // [(max_path_edges+1)][d], goal first
+  float* path_actions;              // [max_path_edges][m]
+  float* states;                    // [d][n_cap]  component-major
+  float* actions;                   // [m][n_cap]
+  int* parents;                     // [n_cap]
+  float* costs;                     // [n_cap]
+  const float* obs;                 // packed obstacles (see state_ok)
+  unsigned long long* partial;      // [G][K] packed (d2 bits << 32 | node)
+  float* stg;                       // survivor staging, S = G_roll*256 entries
+  int* counts;                      // [G_roll] survivors per rollout workgroup
+  unsigned long long* goalmin;      // [G_roll] packed (cost bits << 32 | j)
+  int* trace;                       // nullable: per-iteration records
+  long long trace_words;            // int32 words per record
+  long long trace_iters;            // records available
+  long long max_iters;              // <= 0: no limit
+  long long max_rounds;             // <= 0: no limit
+  long long budget_ticks;           // <= 0: no budget
+  long long guard_ticks;            // hard limit on the call's device time
+  long long barrier_timeout_ticks;  // give up on a grid barrier after this long
+};
+
+__device__ __forceinline__ unsigned long long pack_key(float v, uint32_t idx) {
+  return ((unsigned long long)__float_as_uint(v) << 32) | (unsigned long long)idx;
+}
+
+// Grid-wide barrier with a bounded wait.  Workgroup 0 collects the arrival
+// flags and publishes a release word (generation << 1 | failed).  Returns
+// false if any wait timed out; every workgroup then leaves the kernel.
+__device__ __forceinline__ bool grid_barrier(const KArgs& a, uint32_t& gen, int* s_fail) {
+  ++gen;
+  __syncthreads();
+  const int G = gridDim.x;
+  if (G == 1) return true;
+  const uint32_t target = gen & 0x7fffffffu;
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) *s_fail = 0;
+    __syncthreads();
+    for (int i = threadIdx.x + 1; i < G; i += NT) {
+      long long limit = 0;
+      while (__hip_atomic_load(&a.bar_flags[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) !=
+             target) {
+        const long long now = wall_clock64();
+        if (limit == 0) {
+          limit = now + a.barrier_timeout_ticks;
+        } else if (now > limit) {
+          *s_fail = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_store(&a.hdr->release, (target << 1) | (uint32_t)(*s_fail != 0),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  } else if (threadIdx.x == 0) {
+    *s_fail = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(&a.bar_flags[blockIdx.x], target, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    const long long limit = wall_clock64() + a.barrier_timeout_ticks;
+    while (true) {
+      const uint32_t v = __hip_atomic_load(&a.hdr->release, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+      if ((v >> 1) == target) {
+        *s_fail = (int)(v & 1u);
+        break;
+      }
+      if (wall_clock64() > limit) {
+        *s_fail = 1;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+  return *s_fail == 0;
+}
+
+// Offsets of the trace record fields (int32 words).
+struct TraceView {
+  int* hdr;
+  float* targets;
+  int* parents;
+  float* controls;
+  float* xnew;
+  float* cnew;
+  int* flags;
+  int* slots;
+  __device__ TraceView(int* base, int K, int B, int D, int M) {
+    hdr = base;
+    targets = reinterpret_cast<float*>(base + TRACE_HDR_WORDS);
+    parents = reinterpret_cast<int*>(targets + (size_t)K * D);
+    controls = reinterpret_cast<float*>(parents + K);
+    xnew = controls + (size_t)B * M;
+    cnew = xnew + (size_t)B * D;
+    flags = reinterpret_cast<int*>(cnew + B);
+    slots = flags + B;
+  }
+};
+
+template <int SYS, int QT>
+__global__ __launch_bounds__(NT) void k_plan(KArgs a) {
+  constexpr int D = Sys<SYS>::D, M = Sys<SYS>::M, NP = Sys<SYS>::P;
+  const DevProblem& P = a.P;
+  extern __shared__ float s_obs[];
+  __shared__ float s_tile[D][NT];
+  __shared__ unsigned long long s_best[NT];
+  __shared__ int s_cnt[NT + 1];
+  __shared__ int s_off[NT + 1];
+  __shared__ int s_wave[NT / WAVE];
+  __shared__ unsigned long long s_goal;
+  __shared__ int s_fail;
+  __shared__ int s_misc[2];
+
+  const int tid = threadIdx.x;
+  const int b = blockIdx.x;
+  const int G = gridDim.x;
+  const int B = P.B, A = P.A, K = P.K, GR = P.G_roll;
+  const int S = GR * NT;
+  const size_t NC = (size_t)P.n_cap;
+
+  float* stg_x = a.stg;
+  float* stg_u = stg_x + (size_t)D * S;
+  float* stg_c = stg_u + (size_t)M * S;
+  int* stg_par = reinterpret_cast<int*>(stg_c + S);
+  int* stg_j = stg_par + S;
+  int* stg_f = stg_j + S;
+
+  for (int i = tid; i < P.obs_floats; i += NT) s_obs[i] = a.obs[i];
+
+  // loop state: identical in every workgroup
+  int n = a.hdr->n, round = a.hdr->round, iter = a.hdr->iter;
+  float c_best = a.hdr->c_best;
+  uint32_t gen = a.hdr->bar_gen;
+  int n_sol = a.hdr->n_solutions;
+  long long it_done = 0, rounds_done = 0;
+  int status = 0;
+
+  // workgroup-0 bookkeeping
+  long long t0 = 0, deadline = LLONG_MAX, guard = LLONG_MAX, t_first = -1, t_last = -1;
+  unsigned long long c_exp = 0, c_ins = 0, c_nn = 0;
+  int c_sol = 0;
+  if (b == 0) {
+    t0 = wall_clock64();
+    if (a.budget_ticks > 0) deadline = t0 + a.budget_ticks;
+    guard = t0 + a.guard_ticks;
+  }
+  __syncthreads();
+
+  while (true) {
+    if (a.max_iters > 0 && it_done >= a.max_iters) { status |= PAKR_S_ITERS_DONE; break; }
+    if (a.max_rounds > 0 && rounds_done >= a.max_rounds) { status |= PAKR_S_ROUNDS_DONE; break; }
+    int* trace = (a.trace != nullptr && it_done < a.trace_iters) ? a.trace + it_done * a.trace_words
+                                                                 : nullptr;
+    const int ntiles = (n + NT - 1) / NT;
+    const int G_act = min(G, ntiles);
+
+    // ---------------- phase 1: targets + nearest neighbour -----------------
+    for (int base = 0; base < K; base += NT * QT) {
+      float q[QT][D];
+      float bd[QT];
+      int bi[QT];
+#pragma unroll
+      for (int qq = 0; qq < QT; ++qq) {
+        const int k = base + qq * NT + tid;
+        bd[qq] = INFINITY;
+        bi[qq] = 0;
+        if (k < K) {
+          sample_state<D>(P, (uint32_t)k, (uint32_t)iter, (uint32_t)round, q[qq]);
+          if (trace != nullptr && b == 0) {
+            TraceView tv(trace, K, B, D, M);
+#pragma unroll
+            for (int c = 0; c < D; ++c) tv.targets[(size_t)k * D + c] = q[qq][c];
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < D; ++c) q[qq][c] = 0.0f;
+        }
+      }
+      if (b < G_act) {
+        for (int t = b; t < ntiles; t += G) {
+          const int node0 = t * NT;
+          const int len = min(NT, n - node0);
+          __syncthreads();
+          if (tid < len) {
+#pragma unroll
+            for (int c = 0; c < D; ++c) s_tile[c][tid] = a.states[(size_t)c * NC + node0 + tid];
+          }
+          __syncthreads();
+          for (int i = 0; i < len; ++i) {
+            float pc[D];
+#pragma unroll
+            for (int c = 0; c < D; ++c) pc[c] = s_tile[c][i];
+#pragma unroll
+            for (int qq = 0; qq < QT; ++qq) {
+              float s = 0.0f;
+#pragma unroll
+              for (int c = 0; c < D; ++c) {
+                const float e = q[qq][c] - pc[c];
+                s = fmaf(e, e, s);
+              }
+              if (s < bd[qq]) {
+                bd[qq] = s;
+                bi[qq] = node0 + i;
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int qq = 0; qq < QT; ++qq) {
+          const int k = base + qq * NT + tid;
+          if (k < K) a.partial[(size_t)b * K + k] = pack_key(bd[qq], (uint32_t)bi[qq]);
+        }
+      }
+    }
+    if (b == 0 && tid == 0) {
+      const long long now = wall_clock64();
+      const int stop = now >= deadline ? 1 : (now >= guard ? 2 : 0);
+      __hip_atomic_store(&a.hdr->stop[it_done & 1], stop, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (!grid_barrier(a, gen, &s_fail)) {
+      if (tid == 0) __hip_atomic_store(&a.hdr->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
+    if (tid == 0)
+      s_misc[0] = __hip_atomic_load(&a.hdr->stop[it_done & 1], __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    if (s_misc[0] != 0) {
+      status |= (s_misc[0] == 1) ? PAKR_S_BUDGET_EXPIRED : PAKR_S_DEVICE_ERROR;
+      break;
+    }
+
+    // ---------------- phase 2: controls, rollout, validity, prune ---------
+    if (b < GR) {
+      const int j0 = b * NT;
+      const int j1 = min(B, j0 + NT);
+      const int k0 = j0 / A;
+      const int nql = (j1 - 1) / A - k0 + 1;
+      for (int i = tid; i < nql; i += NT) s_best[i] = ~0ull;
+      if (tid == 0) s_goal = ~0ull;
+      __syncthreads();
+      const int tot = nql * G_act;
+      for (int idx = tid; idx < tot; idx += NT) {
+        const int qi = idx % nql;
+        const int src = idx / nql;
+        atomicMin(&s_best[qi], a.partial[(size_t)src * K + k0 + qi]);
+      }
+      __syncthreads();
+
+      const int j = j0 + tid;
+      const bool active = j < B;
+      float x[D], u[M];
+      float cost = 0.0f;
+      bool valid = false, prune_ok = false, in_goal = false;
+      int parent = 0, k = 0, br = 0;
+      if (active) {
+        k = j / A;
+        br = j - k * A;
+        parent = (int)(uint32_t)(s_best[k - k0] & 0xffffffffull);
+        sample_control<M>(P, (uint32_t)k, (uint32_t)br, (uint32_t)iter, (uint32_t)round, u);
+#pragma unroll
+        for (int c = 0; c < D; ++c) x[c] = a.states[(size_t)c * NC + parent];
+        const float c_par = a.costs[parent];
+        valid = true;
+        float len = 0.0f;
+        const bool path_len = P.cost_kind == PAKR_COST_PATH_LENGTH;
+        for (int t = 0; t < P.T; ++t) {
+          float xp[NP];
+#pragma unroll
+          for (int c = 0; c < NP; ++c) xp[c] = x[c];
+          rk4_step<SYS>(P, x, u, P.dt);
+          if (path_len) {
+            float s2 = 0.0f;
+#pragma unroll
+            for (int c = 0; c < NP; ++c) {
+              const float e = x[c] - xp[c];
+              s2 += e * e;
+            }
+            len += sqrtf(s2);
+          }
+          valid = state_ok<SYS>(P, x, s_obs) && valid;
+        }
+        cost = c_par + (path_len ? len : P.edge_duration);
+        const float dist = sqrtf(goal_dist2<SYS>(P, x));
+        prune_ok = (cost + heuristic<SYS>(P, dist)) < c_best;
+        in_goal = dist <= P.goal_r;
+      }
+      const bool keep = active && valid && prune_ok;
+      const unsigned long long mask = __ballot(keep);
+      const int lane = tid & (WAVE - 1), wv = tid / WAVE;
+      const int wrank = __popcll(mask & ((1ull << lane) - 1ull));
+      if (lane == 0) s_wave[wv] = __popcll(mask);
+      __syncthreads();
+      int base_r = 0, total = 0;
+#pragma unroll
+      for (int w = 0; w < NT / WAVE; ++w) {
+        base_r += (w < wv) ? s_wave[w] : 0;
+        total += s_wave[w];
+      }
+      if (keep) {
+        const int e = b * NT + base_r + wrank;
+#pragma unroll
+        for (int c = 0; c < D; ++c) stg_x[(size_t)c * S + e] = x[c];
+#pragma unroll
+        for (int c = 0; c < M; ++c) stg_u[(size_t)c * S + e] = u[c];
+        stg_c[e] = cost;
+        stg_par[e] = parent;
+        stg_j[e] = j;
+        stg_f[e] = in_goal ? F_GOAL : 0;
+        if (in_goal) atomicMin(&s_goal, pack_key(cost, (uint32_t)j));
+      }
+      __syncthreads();
+      if (tid == 0) {
+        a.counts[b] = total;
+        a.goalmin[b] = s_goal;
+      }
+      if (trace != nullptr && active) {
+        TraceView tv(trace, K, B, D, M);
+        if (br == 0) tv.parents[k] = parent;
+#pragma unroll
+        for (int c = 0; c < M; ++c) tv.controls[(size_t)j * M + c] = u[c];
+#pragma unroll
+        for (int c = 0; c < D; ++c) tv.xnew[(size_t)j * D + c] = x[c];
+        tv.cnew[j] = cost;
+        tv.flags[j] = (valid ? F_VALID : 0) | (prune_ok ? F_PRUNE_OK : 0) | (keep ? F_KEEP : 0) |
+                      (in_goal ? F_GOAL : 0);
+        tv.slots[j] = -1;
+      }
+    }
+    if (!grid_barrier(a, gen, &s_fail)) {
+      if (tid == 0) __hip_atomic_store(&a.hdr->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
+
+    // ---------------- phase 3: insert + goal + round bookkeeping ----------
+    if (tid < GR) s_cnt[tid] = a.counts[tid];
+    __syncthreads();
+    if (tid == 0) {
+      int acc = 0;
+      for (int w = 0; w < GR; ++w) {
+        s_off[w] = acc;
+        acc += s_cnt[w];
+      }
+      s_off[GR] = acc;
+    }
+    __syncthreads();
+    const int survivors = s_off[GR];
+    const int n0 = n;
+    const int n_ins = min(survivors, P.n_cap - n0);
+    const int n1 = n0 + n_ins;
+    if (n_ins > 0) {
+      const int t_lo = n0 / NT, t_hi = (n1 - 1) / NT;
+      int t = t_lo + ((b - t_lo % G) % G + G) % G;
+      for (; t <= t_hi; t += G) {
+        const int s = t * NT + tid;
+        if (s >= n0 && s < n1) {
+          const int r = s - n0;
+          int lo = 0, hi = GR - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= r) lo = mid; else hi = mid - 1;
+          }
+          const int e = lo * NT + (r - s_off[lo]);
+#pragma unroll
+          for (int c = 0; c < D; ++c) a.states[(size_t)c * NC + s] = stg_x[(size_t)c * S + e];
+#pragma unroll
+          for (int c = 0; c < M; ++c) a.actions[(size_t)c * NC + s] = stg_u[(size_t)c * S + e];
+          a.parents[s] = stg_par[e];
+          a.costs[s] = stg_c[e];
+          if (trace != nullptr) {
+            TraceView tv(trace, K, B, D, M);
+            tv.slots[stg_j[e]] = s;
+          }
+        }
+      }
+    }
+    // cheapest inserted goal candidate, ties to the lowest j
+    unsigned long long key = ~0ull;
+    if (tid < GR) {
+      const int off = s_off[tid], cnt = s_cnt[tid];
+      if (off + cnt <= n_ins) {
+        key = a.goalmin[tid];
+      } else if (off < n_ins) {
+        for (int l = 0; l < n_ins - off; ++l) {
+          const int e = tid * NT + l;
+          if (stg_f[e] & F_GOAL) {
+            const unsigned long long kk = pack_key(stg_c[e], (uint32_t)stg_j[e]);
+            key = kk < key ? kk : key;
+          }
+        }
+      }
+    }
+    if (tid == 0) {
+      s_goal = ~0ull;
+      s_misc[1] = -1;
+    }
+    __syncthreads();
+    if (key != ~0ull) atomicMin(&s_goal, key);
+    __syncthreads();
+    const unsigned long long gk = s_goal;
+    const bool goal = gk != ~0ull;
+    int goal_j = -1, goal_e = -1, goal_slot = -1;
+    float goal_cost = 0.0f;
+    if (goal) {
+      goal_j = (int)(uint32_t)(gk & 0xffffffffull);
+      goal_cost = __uint_as_float((uint32_t)(gk >> 32));
+      const int wg = goal_j / NT;
+      if (tid < s_cnt[wg] && stg_j[wg * NT + tid] == goal_j) s_misc[1] = tid;
+      __syncthreads();
+      goal_e = wg * NT + s_misc[1];
+      goal_slot = n0 + s_off[wg] + s_misc[1];
+    }
+    int end = END_NONE;
+    if (goal) end = END_GOAL;
+    else if (n1 >= P.n_cap) end = END_TREE_FULL;
+    else if (iter + 1 >= P.max_iters_per_round) end = END_ITER_CAP;
+
+    if (b == 0 && tid == 0) {
+      c_exp += (unsigned long long)B;
+      c_ins += (unsigned long long)n_ins;
+      c_nn += (unsigned long long)K * (unsigned long long)n0;
+      if (trace != nullptr) {
+        int* h = trace;
+        h[0] = round;
+        h[1] = iter;
+        h[2] = n0;
+        h[3] = n1;
+        h[4] = goal_j;
+        h[5] = goal_slot;
+        h[6] = end;
+        h[7] = __float_as_int(c_best);
+        h[8] = __float_as_int(goal ? goal_cost : c_best);
+        h[9] = survivors;
+      }
+      if (goal) {
+        const long long tnow = wall_clock64() - t0;
+        if (t_first < 0) t_first = tnow;
+        t_last = tnow;
+        if (n_sol < MAX_SOLUTIONS) {
+          DevSolution& so = a.sols[n_sol];
+          so.round = round;
+          so.iter = iter;
+          so.node = goal_slot;
+          so.n_nodes = n1;
+          so.total_iter = (long long)a.hdr->total_iters + it_done;
+          so.cost = goal_cost;
+          so.t = tnow;
+        }
+        ++n_sol;
+        ++c_sol;
+        // ExtractPath: walk the parent chain, goal first
+        float* ps = a.path_states;
+        float* pa = a.path_actions;
+#pragma unroll
+        for (int c = 0; c < D; ++c) ps[c] = stg_x[(size_t)c * S + goal_e];
+#pragma unroll
+        for (int c = 0; c < M; ++c) pa[c] = stg_u[(size_t)c * S + goal_e];
+        int p = stg_par[goal_e];
+        int ne = 1;
+        int trunc = 0;
+        while (p > 0) {
+          if (ne >= P.max_path_edges) {
+            trunc = 1;
+            break;
+          }
+#pragma unroll
+          for (int c = 0; c < D; ++c) ps[(size_t)ne * D + c] = a.states[(size_t)c * NC + p];
+#pragma unroll
+          for (int c = 0; c < M; ++c) pa[(size_t)ne * M + c] = a.actions[(size_t)c * NC + p];
+          p = a.parents[p];
+          ++ne;
+        }
+#pragma unroll
+        for (int c = 0; c < D; ++c) ps[(size_t)ne * D + c] = a.states[(size_t)c * NC];
+        a.hdr->best_edges = ne;
+        a.hdr->best_node = goal_slot;
+        a.hdr->best_cost = goal_cost;
+        a.hdr->path_truncated = trunc;
+      }
+    }
+
+    if (goal) c_best = goal_cost;
+    if (end == END_TREE_FULL) status |= PAKR_S_TREE_FULL;
+    if (end == END_ITER_CAP) status |= PAKR_S_ITER_CAP;
+    if (end != END_NONE) {
+      ++round;
+      iter = 0;
+      n = 1;
+      ++rounds_done;
+    } else {
+      ++iter;
+      n = n1;
+    }
+    ++it_done;
+  }
+
+  if (b == 0 && tid == 0) {
+    DevHeader* h = a.hdr;
+    h->n = n;
+    h->round = round;
+    h->iter = iter;
+    h->c_best = c_best;
+    h->n_solutions = n_sol;
+    h->bar_gen = gen;
+    h->total_iters += (unsigned long long)it_done;
+    h->expansions += c_exp;
+    h->insertions += c_ins;
+    h->nn_pairs += c_nn;
+    h->t_start = t0;
+    h->t_end = wall_clock64();
+    h->t_first = t_first;
+    h->t_last = t_last;
+    h->call_iters = (int)it_done;
+    h->call_rounds = (int)rounds_done;
+    h->call_solutions = c_sol;
+    h->status = status | (n_sol > 0 ? PAKR_S_SOLVED : 0);
+  }
+}
+
+// Writes the root (x_init, no action, cost 0) and resets the loop state.
+__global__ void k_init(DevHeader* hdr, uint32_t* bar_flags, int n_flags, float* states,
+                       float* actions, int* parents, float* costs, int n_cap, int d, int m,
+                       float x0, float x1, float x2, float x3, float x4, float x5, float x6,
+                       float x7, float x8, float x9, float x10, float x11, float c0) {
+  const int tid = threadIdx.x;
+  for (int i = tid; i < n_flags; i += blockDim.x) bar_flags[i] = 0u;
+  if (tid == 0) {
+    const float xi[12] = {x0, x1, x2, x3, x4, x5, x6, x7, x8, x9, x10, x11};
+    for (int c = 0; c < d; ++c) states[(size_t)c * n_cap] = xi[c];
+    for (int c = 0; c < m; ++c) actions[(size_t)c * n_cap] = 0.0f;
+    parents[0] = -1;
+    costs[0] = 0.0f;
+    DevHeader z = {};
+    z.n = 1;
+    z.c_best = c0;
+    z.best_edges = -1;
+    z.best_node = -1;
+    z.t_first = -1;
+    z.t_last = -1;
+    *hdr = z;
+  }
+}
+
+}  // namespace pakr

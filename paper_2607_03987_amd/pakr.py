@@ -1,0 +1,341 @@
+"""Python binding of libpakr (include/pakr.h): argument marshalling only.
+
+Every step of the planner runs in the HIP kernels of libpakr.so.  PyTorch
+provides device memory (the plan workspace and trace buffers are torch
+tensors) and the HIP stream.  There is no fallback: if the library is not
+built, or no GPU is present, the calls raise.
+
+The function names follow the C ABI: ``workspace_size``, ``plan_init``,
+``expand``, ``replan``, ``status``, ``solutions``, ``extract_path``,
+``copy_tree``; ``Plan`` bundles them.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from typing import Optional
+
+import numpy as np
+
+from . import workloads as W
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpakr.so")
+
+MAX_D, MAX_M = 12, 4
+PAKR_OK = 0
+ERRORS = {0: "PAKR_OK", -1: "PAKR_E_INVALID_ARG", -2: "PAKR_E_START_INVALID",
+          -3: "PAKR_E_GOAL_INVALID", -4: "PAKR_E_WORKSPACE_TOO_SMALL", -5: "PAKR_E_HIP",
+          -6: "PAKR_E_NO_SOLUTION", -7: "PAKR_E_BUFFER_TOO_SMALL", -8: "PAKR_E_DEVICE"}
+S_SOLVED, S_BUDGET_EXPIRED, S_ROUNDS_DONE, S_ITERS_DONE = 1, 2, 4, 8
+S_TREE_FULL, S_ITER_CAP, S_DEVICE_ERROR = 16, 32, 64
+F_VALID, F_PRUNE_OK, F_KEEP, F_GOAL = 1, 2, 4, 8
+TRACE_HDR_WORDS = 16
+
+EXPORTED = ["pakr_workspace_size", "pakr_plan_init", "pakr_plan_destroy", "pakr_trace_bytes",
+            "pakr_expand", "pakr_replan", "pakr_status", "pakr_solutions", "pakr_extract_path",
+            "pakr_copy_tree", "pakr_last_error", "pakr_error_string"]
+
+
+class PakrError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class System(C.Structure):
+    _fields_ = [("id", C.c_int), ("d", C.c_int), ("m", C.c_int), ("dyn", C.c_float * 8),
+                ("sample_lo", C.c_float * MAX_D), ("sample_hi", C.c_float * MAX_D),
+                ("u_lo", C.c_float * MAX_M), ("u_hi", C.c_float * MAX_M),
+                ("lim_lo", C.c_float * MAX_D), ("lim_hi", C.c_float * MAX_D),
+                ("vnorm_max", C.c_float)]
+
+
+class Scene(C.Structure):
+    _fields_ = [("npos", C.c_int), ("ws_lo", C.c_float * 3), ("ws_hi", C.c_float * 3),
+                ("n_box", C.c_int), ("box_c", C.POINTER(C.c_float)), ("box_h", C.POINTER(C.c_float)),
+                ("n_sphere", C.c_int), ("sph_c", C.POINTER(C.c_float)),
+                ("sph_r", C.POINTER(C.c_float))]
+
+
+class Goal(C.Structure):
+    _fields_ = [("center", C.c_float * 3), ("radius", C.c_float)]
+
+
+class Params(C.Structure):
+    _fields_ = [("B", C.c_int), ("A", C.c_int), ("T", C.c_int), ("dt", C.c_float),
+                ("n_cap", C.c_int), ("cost_kind", C.c_int), ("heuristic_kind", C.c_int),
+                ("h_speed", C.c_float), ("cost_bound", C.c_double), ("seed", C.c_uint64),
+                ("query_id", C.c_uint32), ("max_iters_per_round", C.c_int), ("grid", C.c_int),
+                ("max_path_edges", C.c_int)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_nodes", C.c_int), ("round", C.c_int), ("iter", C.c_int), ("status", C.c_int),
+                ("n_solutions", C.c_int), ("grid", C.c_int), ("total_iters", C.c_longlong),
+                ("expansions", C.c_longlong), ("insertions", C.c_longlong),
+                ("nn_pairs", C.c_longlong), ("c_best", C.c_double), ("call_ms", C.c_double),
+                ("t_first_ms", C.c_double), ("t_last_ms", C.c_double), ("call_iters", C.c_int),
+                ("call_rounds", C.c_int), ("call_solutions", C.c_int), ("reserved", C.c_int)]
+
+
+class Solution(C.Structure):
+    _fields_ = [("round", C.c_int), ("iter", C.c_int), ("node", C.c_int), ("n_nodes", C.c_int),
+                ("total_iter", C.c_longlong), ("cost", C.c_double), ("t_ms", C.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Load libpakr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        import torch  # noqa: F401  -- the HIP runtime comes from torch's process image
+        L = C.CDLL(LIB_PATH, mode=C.RTLD_GLOBAL)
+        vp, sz = C.c_void_p, C.c_size_t
+        L.pakr_workspace_size.argtypes = [C.POINTER(System), C.POINTER(Params), C.POINTER(Scene)]
+        L.pakr_workspace_size.restype = sz
+        L.pakr_plan_init.argtypes = [C.POINTER(System), C.POINTER(Scene), C.POINTER(C.c_float),
+                                     C.POINTER(Goal), C.POINTER(Params), vp, sz, vp,
+                                     C.POINTER(vp)]
+        L.pakr_plan_init.restype = C.c_int
+        L.pakr_plan_destroy.argtypes = [vp]
+        L.pakr_plan_destroy.restype = None
+        L.pakr_trace_bytes.argtypes = [vp, C.c_int]
+        L.pakr_trace_bytes.restype = sz
+        L.pakr_expand.argtypes = [vp, C.c_int, vp, sz]
+        L.pakr_expand.restype = C.c_int
+        L.pakr_replan.argtypes = [vp, C.c_double, C.c_int, C.c_longlong]
+        L.pakr_replan.restype = C.c_int
+        L.pakr_status.argtypes = [vp, C.POINTER(Stats)]
+        L.pakr_status.restype = C.c_int
+        L.pakr_solutions.argtypes = [vp, C.POINTER(Solution), C.c_int, C.POINTER(C.c_int)]
+        L.pakr_solutions.restype = C.c_int
+        L.pakr_extract_path.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_int,
+                                        C.POINTER(C.c_int), C.POINTER(C.c_double)]
+        L.pakr_extract_path.restype = C.c_int
+        L.pakr_copy_tree.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_float),
+                                     C.POINTER(C.c_int), C.POINTER(C.c_float), C.c_int,
+                                     C.POINTER(C.c_int)]
+        L.pakr_copy_tree.restype = C.c_int
+        L.pakr_last_error.argtypes = [vp]
+        L.pakr_last_error.restype = C.c_char_p
+        L.pakr_error_string.argtypes = [C.c_int]
+        L.pakr_error_string.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _fp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+class CQuery:
+    """The C structs of one Problem (holds the host arrays alive)."""
+
+    def __init__(self, prob: W.Problem, grid: int = 0, max_path_edges: int = 0):
+        self.prob = prob
+        s = System()
+        s.id, s.d, s.m = prob.system, prob.d, prob.m
+        for i in range(8):
+            s.dyn[i] = float(prob.dyn[i])
+        for i in range(prob.d):
+            s.sample_lo[i], s.sample_hi[i] = float(prob.sample_lo[i]), float(prob.sample_hi[i])
+            s.lim_lo[i], s.lim_hi[i] = float(prob.lim_lo[i]), float(prob.lim_hi[i])
+        for i in range(prob.m):
+            s.u_lo[i], s.u_hi[i] = float(prob.u_lo[i]), float(prob.u_hi[i])
+        s.vnorm_max = float(prob.vnorm_max)
+        self.system = s
+        P = prob.npos
+        self._bc = np.ascontiguousarray(prob.box_c, np.float32).reshape(-1)
+        self._bh = np.ascontiguousarray(prob.box_h, np.float32).reshape(-1)
+        self._sc = np.ascontiguousarray(prob.sph_c, np.float32).reshape(-1)
+        self._sr = np.ascontiguousarray(prob.sph_r, np.float32).reshape(-1)
+        sc = Scene()
+        sc.npos = P
+        for c in range(P):
+            sc.ws_lo[c], sc.ws_hi[c] = float(prob.ws_lo[c]), float(prob.ws_hi[c])
+        sc.n_box, sc.box_c, sc.box_h = int(prob.box_c.shape[0]), _fp(self._bc), _fp(self._bh)
+        sc.n_sphere, sc.sph_c, sc.sph_r = int(prob.sph_r.shape[0]), _fp(self._sc), _fp(self._sr)
+        self.scene = sc
+        g = Goal()
+        for c in range(P):
+            g.center[c] = float(prob.goal_c[c])
+        g.radius = float(prob.goal_r)
+        self.goal = g
+        self.x_init = np.ascontiguousarray(prob.x_init, np.float32)
+        p = Params()
+        p.B, p.A, p.T, p.dt, p.n_cap = prob.B, prob.A, prob.T, float(prob.dt), prob.n_cap
+        p.cost_kind, p.heuristic_kind, p.h_speed = prob.cost_kind, prob.h_kind, float(prob.h_speed)
+        p.cost_bound = float(prob.c0)
+        p.seed, p.query_id = int(prob.seed), int(prob.qid)
+        p.max_iters_per_round = int(prob.max_iters_per_round)
+        p.grid, p.max_path_edges = int(grid), int(max_path_edges)
+        self.params = p
+
+
+def workspace_size(q: CQuery) -> int:
+    return int(load().pakr_workspace_size(C.byref(q.system), C.byref(q.params), C.byref(q.scene)))
+
+
+def _check(rc: int, handle=None):
+    if rc != PAKR_OK:
+        msg = load().pakr_last_error(handle)
+        raise PakrError(rc, msg.decode() if msg else "")
+
+
+def plan_init(q: CQuery, d_workspace: int, ws_bytes: int, stream: int) -> int:
+    h = C.c_void_p()
+    rc = load().pakr_plan_init(C.byref(q.system), C.byref(q.scene), _fp(q.x_init), C.byref(q.goal),
+                               C.byref(q.params), C.c_void_p(d_workspace), ws_bytes,
+                               C.c_void_p(stream), C.byref(h))
+    _check(rc, None)
+    return h.value
+
+
+class Plan:
+    """One planning query on the current GPU.
+
+    The workspace (tree, work buffers) is a torch uint8 tensor on the device;
+    calls are enqueued on torch's current stream.
+    """
+
+    def __init__(self, prob: W.Problem, grid: int = 0, max_path_edges: int = 0, device=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("libpakr needs a ROCm GPU; none is visible")
+        self.torch = torch
+        self.prob = prob
+        self.q = CQuery(prob, grid=grid, max_path_edges=max_path_edges)
+        self.device = torch.device(device or "cuda")
+        nbytes = workspace_size(self.q)
+        if nbytes == 0:
+            raise PakrError(-1, "workspace_size rejected the query")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) & ~255
+        self.stream = torch.cuda.current_stream(self.device)
+        self.h = plan_init(self.q, self._ws_ptr, nbytes, self.stream.cuda_stream)
+        self.K, self.B, self.d, self.m = prob.K, prob.B, prob.d, prob.m
+
+    def close(self):
+        h = getattr(self, "h", None)
+        if h:
+            load().pakr_plan_destroy(h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --- C calls -----------------------------------------------------------
+    def trace_bytes(self, n_iters: int) -> int:
+        return int(load().pakr_trace_bytes(self.h, n_iters))
+
+    def expand(self, n_iters: int, trace: bool = False):
+        """Run n_iters iterations; with trace=True return the decoded records."""
+        buf = None
+        nbytes = 0
+        if trace:
+            nbytes = self.trace_bytes(n_iters)
+            buf = self.torch.zeros(nbytes // 4, dtype=self.torch.int32, device=self.device)
+        _check(load().pakr_expand(self.h, n_iters, C.c_void_p(buf.data_ptr() if trace else 0),
+                                  nbytes), self.h)
+        if not trace:
+            return None
+        self.torch.cuda.synchronize(self.device)
+        return self.decode_trace(buf.cpu().numpy(), n_iters)
+
+    def replan(self, budget_ms: float = 0.0, max_rounds: int = 0, max_iters: int = 0):
+        _check(load().pakr_replan(self.h, float(budget_ms), int(max_rounds), int(max_iters)), self.h)
+
+    def status(self) -> dict:
+        s = Stats()
+        _check(load().pakr_status(self.h, C.byref(s)), self.h)
+        return {f[0]: getattr(s, f[0]) for f in Stats._fields_}
+
+    def solutions(self) -> list:
+        n = C.c_int(0)
+        _check(load().pakr_solutions(self.h, None, 0, C.byref(n)), self.h)
+        arr = (Solution * max(n.value, 1))()
+        _check(load().pakr_solutions(self.h, arr, n.value, C.byref(n)), self.h)
+        cnt = min(n.value, 1024)
+        return [{f[0]: getattr(arr[i], f[0]) for f in Solution._fields_} for i in range(cnt)]
+
+    def extract_path(self):
+        ne = C.c_int(0)
+        cost = C.c_double(0)
+        rc = load().pakr_extract_path(self.h, None, None, 0, C.byref(ne), C.byref(cost))
+        if rc == -6:
+            return None
+        if rc not in (0, -7):
+            _check(rc, self.h)
+        n = ne.value
+        states = np.zeros((n + 1, self.d), np.float32)
+        actions = np.zeros((max(n, 1), self.m), np.float32)
+        _check(load().pakr_extract_path(self.h, _fp(states), _fp(actions), n, C.byref(ne),
+                                        C.byref(cost)), self.h)
+        return states, actions[:n], cost.value
+
+    def copy_tree(self):
+        n = C.c_int(0)
+        _check(load().pakr_copy_tree(self.h, None, None, None, None, 0, C.byref(n)), self.h)
+        nn = n.value
+        states = np.zeros((nn, self.d), np.float32)
+        actions = np.zeros((nn, self.m), np.float32)
+        parents = np.zeros(nn, np.int32)
+        costs = np.zeros(nn, np.float32)
+        _check(load().pakr_copy_tree(self.h, _fp(states), _fp(actions),
+                                     parents.ctypes.data_as(C.POINTER(C.c_int)), _fp(costs), nn,
+                                     C.byref(n)), self.h)
+        return states, actions, parents, costs
+
+    # --- trace decoding ----------------------------------------------------
+    def decode_trace(self, words: np.ndarray, n_iters: int) -> list:
+        K, B, d, m = self.K, self.B, self.d, self.m
+        per = TRACE_HDR_WORDS + K * d + K + B * m + B * d + 3 * B
+        out = []
+        for i in range(n_iters):
+            w = words[i * per:(i + 1) * per]
+            h = w[:TRACE_HDR_WORDS]
+            o = TRACE_HDR_WORDS
+            f32 = lambda a: a.view(np.float32)
+            targets = f32(w[o:o + K * d]).reshape(K, d); o += K * d
+            parents = w[o:o + K].copy(); o += K
+            controls = f32(w[o:o + B * m]).reshape(B, m); o += B * m
+            xnew = f32(w[o:o + B * d]).reshape(B, d); o += B * d
+            cnew = f32(w[o:o + B]).copy(); o += B
+            flags = w[o:o + B].copy(); o += B
+            slots = w[o:o + B].copy(); o += B
+            out.append(dict(round=int(h[0]), iter=int(h[1]), n0=int(h[2]), n1=int(h[3]),
+                            goal_j=int(h[4]), goal_slot=int(h[5]), end=int(h[6]),
+                            c_best_before=float(h[7:8].view(np.float32)[0]),
+                            c_best_after=float(h[8:9].view(np.float32)[0]),
+                            survivors=int(h[9]), targets=targets.copy(), parents=parents,
+                            controls=controls.copy(), xnew=xnew.copy(), cnew=cnew, flags=flags,
+                            slots=slots))
+        return out
+
+
+# C-ABI names at module level
+def expand(plan: Plan, n_iters: int, trace: bool = False):
+    return plan.expand(n_iters, trace)
+
+
+def replan(plan: Plan, budget_ms: float = 0.0, max_rounds: int = 0, max_iters: int = 0):
+    return plan.replan(budget_ms, max_rounds, max_iters)
+
+
+def status(plan: Plan) -> dict:
+    return plan.status()
+
+
+def extract_path(plan: Plan):
+    return plan.extract_path()

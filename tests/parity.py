@@ -1,0 +1,78 @@
+"""Step parity between the HIP planner and the FP64 reference.
+
+For each GPU iteration the reference is re-seeded with the GPU's float32 tree
+as it stood before the iteration (the snapshot is the first n0 slots of the
+tree), recomputes the iteration in double precision, and adopts the GPU's
+choice only where its own decision is a near tie (|margin| <= 1e-5, see the
+reference's steering contract).  Then:
+
+* targets and controls must be bit-identical (sampled values);
+* parents, validity / prune / goal flags, insertion slots, the new node count
+  and the goal candidate must be identical (no mismatch on a clear decision);
+* final states and costs of valid candidates must agree within 1e-4 relative.
+"""
+import numpy as np
+
+import oracle
+from paper_2607_03987_amd import pakr
+
+REL_TOL = 1e-4
+
+
+def rel_err(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return np.abs(a - b) / np.maximum(1.0, np.abs(b))
+
+
+def compare_iteration(prob, tr, rep, ctx=""):
+    """Compare one decoded GPU trace record with the reference report."""
+    B = prob.B
+    np.testing.assert_array_equal(tr["targets"].view(np.uint32), rep.targets.view(np.uint32),
+                                  err_msg=f"{ctx} targets")
+    np.testing.assert_array_equal(tr["controls"].view(np.uint32), rep.controls.view(np.uint32),
+                                  err_msg=f"{ctx} controls")
+    assert rep.n_mismatch == 0, f"{ctx} {rep.n_mismatch} clear-cut decisions differ"
+    np.testing.assert_array_equal(tr["parents"], rep.parents, err_msg=f"{ctx} parents")
+    gv = (tr["flags"] & pakr.F_VALID) != 0
+    ov = (rep.flags & oracle.F_VALID) != 0
+    np.testing.assert_array_equal(gv, ov, err_msg=f"{ctx} valid flags")
+    for gbit, obit, name in [(pakr.F_PRUNE_OK, oracle.F_PRUNE_OK, "prune"),
+                             (pakr.F_GOAL, oracle.F_GOAL, "goal")]:
+        np.testing.assert_array_equal(((tr["flags"] & gbit) != 0)[ov], ((rep.flags & obit) != 0)[ov],
+                                      err_msg=f"{ctx} {name} flags")
+    np.testing.assert_array_equal(tr["slots"], rep.slots, err_msg=f"{ctx} slots")
+    assert tr["n1"] == rep.n1, f"{ctx} n1 {tr['n1']} vs {rep.n1}"
+    assert tr["goal_j"] == rep.goal_j, f"{ctx} goal {tr['goal_j']} vs {rep.goal_j}"
+    assert tr["end"] == rep.end, f"{ctx} end {tr['end']} vs {rep.end}"
+    if ov.any():
+        e = rel_err(tr["xnew"][ov], rep.xnew[ov]).max()
+        assert e <= REL_TOL, f"{ctx} state rel err {e}"
+        ec = rel_err(tr["cnew"][ov], rep.cnew[ov]).max()
+        assert ec <= REL_TOL, f"{ctx} cost rel err {ec}"
+    return dict(steered=rep.n_steered, valid=int(ov.sum()), kept=int((tr["slots"] >= 0).sum()),
+                max_state_err=float(rel_err(tr["xnew"][ov], rep.xnew[ov]).max()) if ov.any() else 0.0)
+
+
+def step_parity(prob, n_iters, grid=0, log=None):
+    """Run n_iters GPU iterations one at a time; replay each in the reference."""
+    plan = pakr.Plan(prob, grid=grid)
+    orc = oracle.OraclePlan(prob)
+    stats = []
+    c_best = float(prob.c0)
+    for i in range(n_iters):
+        st = plan.status()
+        states, actions, parents, costs = plan.copy_tree()
+        c_gpu = st["c_best"]
+        orc.load_tree(states, actions, parents, costs, st["round"], st["iter"],
+                      c_gpu if np.isfinite(c_gpu) else np.inf)
+        tr = plan.expand(1, trace=True)[0]
+        assert tr["round"] == st["round"] and tr["iter"] == st["iter"] and tr["n0"] == st["n_nodes"]
+        rep = orc.iterate(steer=dict(parents=tr["parents"], flags=tr["flags"], goal_j=tr["goal_j"]))
+        s = compare_iteration(prob, tr, rep, ctx=f"{prob.name} iter {i} (round {tr['round']})")
+        stats.append(s)
+        if log:
+            log(f"iter {i}: n {tr['n0']}->{tr['n1']} valid {s['valid']} kept {s['kept']} "
+                f"steered {s['steered']} err {s['max_state_err']:.2e} end {tr['end']}")
+    plan.close()
+    return stats

@@ -1,0 +1,123 @@
+"""HIP planner vs the FP64 reference (GPU tests).
+
+Step parity (tests/parity.py) on every system at sizes the reference replays
+in seconds -- several NN tiles, several rollout workgroups, ragged last tiles
+-- plus the degenerate cases: K = 1, B not a multiple of 256, a tree that
+fills up, an iteration cap, no obstacles, an explicit small grid.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2607_03987_amd import pakr, workloads as W
+from tests.parity import compare_iteration, rel_err, step_parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("cfg,kw,iters", [
+    ("c1", {}, 40),
+    ("c1", dict(seed=3, cost_kind=W.COST_DURATION), 30),
+    ("c2", dict(B=1024, A=8, n_cap=40000), 12),
+    ("c3", dict(B=1024, A=16, n_cap=40000), 12),
+    ("c4", dict(B=512, A=16, n_cap=40000), 10),
+])
+def test_step_parity(cfg, kw, iters):
+    prob = W.CONFIGS[cfg](**kw)
+    print(f"case {prob.name} {kw}", flush=True)
+    stats = step_parity(prob, iters, log=_log)
+    assert sum(s["valid"] for s in stats) > 0
+
+
+@pytest.mark.parametrize("kw", [
+    dict(B=300, A=3, n_cap=5000),          # ragged: B not a multiple of 256, K = 100
+    dict(B=8, A=8, n_cap=2000),            # K = 1
+    dict(B=256, A=1, n_cap=3000),          # A = 1
+    dict(B=256, A=4, n_cap=300),           # the tree fills up
+    dict(B=256, A=4, max_iters_per_round=3),  # iteration cap ends rounds
+])
+def test_step_parity_edge_cases(kw):
+    prob = W.config_c1(**kw)
+    print(f"case c1 {kw}", flush=True)
+    step_parity(prob, 12, log=_log)
+
+
+def test_step_parity_no_obstacles_and_small_grid():
+    prob = W.config_c2(B=512, A=4, n_cap=20000)
+    prob = prob.replace(box_c=prob.box_c[:0], box_h=prob.box_h[:0])
+    print("case c2 no obstacles grid 8", flush=True)
+    step_parity(prob, 8, grid=8, log=_log)
+
+
+def test_expand_in_pieces_equals_one_call():
+    prob = W.config_c1()
+    a = pakr.Plan(prob)
+    b = pakr.Plan(prob)
+    ta = a.expand(20, trace=True)
+    tb = b.expand(7, trace=True) + b.expand(13, trace=True)
+    for x, y in zip(ta, tb):
+        for key in ("parents", "slots", "flags"):
+            np.testing.assert_array_equal(x[key], y[key])
+        np.testing.assert_array_equal(x["xnew"].view(np.uint32), y["xnew"].view(np.uint32))
+    sa, sb = a.copy_tree(), b.copy_tree()
+    for x, y in zip(sa, sb):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_replan_is_deterministic_and_grid_independent():
+    prob = W.config_c1(max_iters_per_round=80)
+    res = []
+    for grid in (0, 4, 1):
+        p = pakr.Plan(prob, grid=grid)
+        p.replan(max_rounds=3)
+        st = p.status()
+        res.append((st["total_iters"], st["insertions"], [s["cost"] for s in p.solutions()],
+                    p.copy_tree()))
+        print(f"grid {grid}: {st['total_iters']} iters, {len(res[-1][2])} solutions", flush=True)
+    for r in res[1:]:
+        assert r[0] == res[0][0] and r[1] == res[0][1] and r[2] == res[0][2]
+        for x, y in zip(r[3], res[0][3]):
+            np.testing.assert_array_equal(x, y)
+
+
+def test_free_running_against_reference():
+    """The reference runs its own FP64 tree, steered only on near ties."""
+    prob = W.config_c1(seed=5, max_iters_per_round=60)
+    plan = pakr.Plan(prob)
+    orc = oracle.OraclePlan(prob)
+    for i in range(80):
+        tr = plan.expand(1, trace=True)[0]
+        rep = orc.iterate(steer=dict(parents=tr["parents"], flags=tr["flags"], goal_j=tr["goal_j"]))
+        compare_iteration(prob, tr, rep, ctx=f"free-running iter {i}")
+    so, sg = orc.solutions(), plan.solutions()
+    assert [(s["round"], s["iter"], s["node"]) for s in so] == \
+           [(s["round"], s["iter"], s["node"]) for s in sg]
+    if so:
+        assert rel_err([s["cost"] for s in sg], [s["cost"] for s in so]).max() <= 1e-4
+
+
+def test_extracted_path_is_feasible():
+    prob = W.config_c1(max_iters_per_round=80)
+    plan = pakr.Plan(prob)
+    plan.replan(max_rounds=2)
+    path = plan.extract_path()
+    assert path is not None
+    states, actions, cost = path
+    assert np.array_equal(states[0], prob.x_init)
+    cp = oracle.CProblem(prob)
+    x = states[0].astype(float)
+    total = 0.0
+    for e in range(actions.shape[0]):
+        ok, xT, c, amb = oracle.edge(cp, x, total, actions[e].astype(float))
+        assert ok or amb
+        assert rel_err(xT, states[e + 1]).max() <= 1e-4
+        x, total = states[e + 1].astype(float), c
+    assert np.linalg.norm(states[-1][:2] - prob.goal_c) <= prob.goal_r * (1 + 1e-6)
+    assert abs(total - cost) <= 1e-4 * max(1.0, cost)
+    sols = plan.solutions()
+    assert sols[-1]["cost"] == pytest.approx(cost)
+    assert all(b["cost"] < a["cost"] for a, b in zip(sols, sols[1:]))
