@@ -1,0 +1,185 @@
+"""Benchmark of the PAKR hot path on one MI355X.
+
+A step is one AO-x query of the 3D double-integrator workload (6D state, 30
+random boxes in [0,10]^3, B 4096, A 8, T 20, dt 0.05, tree capacity 262144,
+duration cost) run on the device for a 200 ms budget: every iteration of
+every round samples, searches the tree, rolls out, checks, prunes and inserts
+on the GPU.  Each step uses its own scene and Philox seed; all plans are
+created (inputs resident in HBM) before the timed region.
+
+Printed: one JSON line with expansions/s over the timed steps, time to first
+and to converged solution, the roofline of the planner kernel and the FP64
+reference's throughput on this host's CPU.
+"""
+import argparse
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "edges expanded/s; median ms to first & converged solution; batched vs plain"
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak
+HBM_PEAK_GBS = 8000.0
+
+
+def flops_per_expansion(prob):
+    """Algorithmic FLOPs of one candidate (add/sub/mul 1, FMA 2, div/sqrt/trig 1).
+
+    Per RK4 step: 6d for the three stage updates, 6d for the final
+    combination, four evaluations of f, the per-step validity arithmetic
+    (speed norm 2P, boxes P each, spheres 3P each) and, for a path-length
+    cost, 3P + 1.  Plus the edge cost, goal distance and heuristic once.
+    """
+    from paper_2607_03987_amd import workloads as W
+    d, P = prob.d, prob.npos
+    f_eval = {W.DI2: 0, W.DI3: 0, W.CAR: 8, W.QUAD: 84}[prob.system]
+    nb, ns = prob.box_c.shape[0], prob.sph_r.shape[0]
+    speed = 2 * P if float(prob.vnorm_max) > 0 else 0
+    step = 12 * d + 4 * f_eval + speed + P * nb + 3 * P * ns
+    if prob.cost_kind == W.COST_PATH_LENGTH:
+        step += 3 * P + 1
+    return prob.T * step + 3 * P + 6
+
+
+def nn_flops_per_pair(prob):
+    return 3 * prob.d
+
+
+def cpu_baseline(prob, seconds):
+    """Time the FP64 reference (single thread) on the same query for ~`seconds`."""
+    import oracle
+    orc = oracle.OraclePlan(prob)
+    t0 = time.perf_counter()
+    iters = 0
+    while time.perf_counter() - t0 < seconds:
+        orc.iterate(report=False)
+        iters += 1
+    dt = time.perf_counter() - t0
+    st = orc.state()
+    return {"value": st["expansions"] / dt, "unit": "expansions/s", "cores": 1, "kind": "oracle",
+            "sample": f"{prob.name} seed {prob.seed}: first {iters} iterations "
+                      f"({st['expansions']} expansions, {st['n_solutions']} solution(s), "
+                      f"tree {st['n']} nodes) in {dt:.1f} s, FP64, one host thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--budget-ms", type=float, default=200.0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--grid", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the planner has no "
+              "multi-GPU path in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2607_03987_amd import _build, pakr, workloads as W
+
+    if not os.path.exists(pakr.LIB_PATH):
+        _build.build(force=True)
+    torch.cuda.set_device(0)
+    dev_name = torch.cuda.get_device_name(0)
+
+    warm = [pakr.Plan(W.config_c2(seed=10_000 + i), grid=args.grid) for i in range(args.warmup)]
+    for p in warm:
+        p.replan(budget_ms=args.budget_ms)
+    torch.cuda.synchronize()
+    for p in warm:
+        p.close()
+
+    probs = [W.config_c2(seed=s) for s in range(args.steps)]
+    plans = [pakr.Plan(pr, grid=args.grid) for pr in probs]
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in plans]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p, (e0, e1) in zip(plans, ev):
+        e0.record(stream)
+        p.replan(budget_ms=args.budget_ms)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    stats = [p.status() for p in plans]
+    sols = [p.solutions() for p in plans]
+    kernel_ms = [e0.elapsed_time(e1) for e0, e1 in ev]
+    expansions = sum(s["expansions"] for s in stats)
+    insertions = sum(s["insertions"] for s in stats)
+    iters = sum(s["total_iters"] for s in stats)
+    nn_pairs = sum(s["nn_pairs"] for s in stats)
+    prob = probs[0]
+    f_exp = flops_per_expansion(prob)
+    f_nn = nn_flops_per_pair(prob)
+    alg_flops = expansions * f_exp + nn_pairs * f_nn
+    mean_kernel_s = statistics.mean(kernel_ms) / 1e3
+    achieved_tflops = alg_flops / len(plans) / mean_kernel_s / 1e12
+    nn_ms = sum(s["nn_ms"] for s in stats)
+    roll_ms = sum(s["rollout_ms"] for s in stats)
+    ins_ms = sum(s["insert_ms"] for s in stats)
+    nn_bytes = nn_pairs / prob.K * prob.d * 4  # each iteration reads the tree once
+    solved = [s for s in sols if s]
+    t_first = [s[0]["t_ms"] for s in solved]
+    t_conv = [s[-1]["t_ms"] for s in solved]
+    c_first = [s[0]["cost"] for s in solved]
+    c_final = [s[-1]["cost"] for s in solved]
+    med = lambda v: statistics.median(v) if v else None
+
+    out = {
+        "metric": METRIC,
+        "value": expansions / wall,
+        "unit": "expansions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "3D double integrator AO-x: [0,10]^3, 30 random boxes side "
+                               "U(0.5,2.5), start (1,1,1), goal ball (9,9,9) r 0.5, duration cost",
+                   "B": prob.B, "A": prob.A, "K": prob.K, "T": prob.T, "dt": float(prob.dt),
+                   "n_cap": prob.n_cap, "budget_ms": args.budget_ms,
+                   "seeds": f"0..{args.steps - 1}", "grid": stats[0]["grid"], "device": dev_name},
+        "time_to_first_ms_median": med(t_first),
+        "time_to_converged_ms_median": med(t_conv),
+        "cost_first_median": med(c_first),
+        "cost_final_median": med(c_final),
+        "solved": f"{len(solved)}/{len(plans)}",
+        "iterations_per_step": iters / len(plans),
+        "insertions_per_s": insertions / wall,
+        "kernel_ms_mean": statistics.mean(kernel_ms),
+        "phase_ms_per_step": {"nn": nn_ms / len(plans), "rollout": roll_ms / len(plans),
+                              "insert": ins_ms / len(plans)},
+        "nn_phase": {"tflops": nn_pairs * f_nn / (nn_ms / 1e3) / 1e12 if nn_ms else None,
+                     "tree_read_gbs": nn_bytes / (nn_ms / 1e3) / 1e9 if nn_ms else None},
+        "rollout_phase": {"tflops": expansions * f_exp / (roll_ms / 1e3) / 1e12 if roll_ms else None,
+                          "flops_per_expansion": f_exp},
+        "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
+                     "traffic": None, "kernel": "k_plan<DI3> (persistent AO-x planner)"},
+        "cpu_baseline": None,
+        "batched": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(W.config_c2(seed=0), args.cpu_seconds)
+    for p in plans:
+        p.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

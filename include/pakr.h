@@ -163,6 +163,9 @@ typedef struct pakr_stats {
   int call_rounds;                 /* rounds completed by the last call                 */
   int call_solutions;              /* solutions found by the last call                  */
   int reserved;
+  double nn_ms;                    /* last call, device time in SampleStates + NN       */
+  double rollout_ms;               /* ... in controls, rollout, validity and prune      */
+  double insert_ms;                /* ... in insertion, goal test and bookkeeping       */
 } pakr_stats;
 
 typedef struct pakr_solution {

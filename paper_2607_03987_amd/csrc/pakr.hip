@@ -539,6 +539,9 @@ int pakr_status(pakr_plan* pl, pakr_stats* out) {
   out->call_iters = h.call_iters;
   out->call_rounds = h.call_rounds;
   out->call_solutions = h.call_solutions;
+  out->nn_ms = (double)h.ticks_nn / pl->ticks_per_ms;
+  out->rollout_ms = (double)h.ticks_roll / pl->ticks_per_ms;
+  out->insert_ms = (double)h.ticks_ins / pl->ticks_per_ms;
   return PAKR_OK;
 }
 

@@ -50,6 +50,8 @@ struct DevHeader {
   uint32_t release;                          // barrier release word
   int stop[2];                               // per-iteration stop decision (parity)
   int pad5;
+  long long ticks_nn, ticks_roll, ticks_ins; // per-phase device time of the last call
+  long long pad6;
 };
 
 struct DevSolution {

@@ -182,6 +182,7 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
   // workgroup-0 bookkeeping
   long long t0 = 0, deadline = LLONG_MAX, guard = LLONG_MAX, t_first = -1, t_last = -1;
   unsigned long long c_exp = 0, c_ins = 0, c_nn = 0;
+  long long tk_nn = 0, tk_roll = 0, tk_ins = 0, tk_mark = 0;
   int c_sol = 0;
   if (b == 0) {
     t0 = wall_clock64();
@@ -197,6 +198,7 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
                                                                  : nullptr;
     const int ntiles = (n + NT - 1) / NT;
     const int G_act = min(G, ntiles);
+    if (b == 0 && tid == 0) tk_mark = wall_clock64();
 
     // ---------------- phase 1: targets + nearest neighbour -----------------
     for (int base = 0; base < K; base += NT * QT) {
@@ -273,6 +275,11 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
     if (s_misc[0] != 0) {
       status |= (s_misc[0] == 1) ? PAKR_S_BUDGET_EXPIRED : PAKR_S_DEVICE_ERROR;
       break;
+    }
+    if (b == 0 && tid == 0) {
+      const long long now = wall_clock64();
+      tk_nn += now - tk_mark;
+      tk_mark = now;
     }
 
     // ---------------- phase 2: controls, rollout, validity, prune ---------
@@ -375,6 +382,12 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
     if (!grid_barrier(a, gen, &s_fail)) {
       if (tid == 0) __hip_atomic_store(&a.hdr->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return;
+    }
+
+    if (b == 0 && tid == 0) {
+      const long long now = wall_clock64();
+      tk_roll += now - tk_mark;
+      tk_mark = now;
     }
 
     // ---------------- phase 3: insert + goal + round bookkeeping ----------
@@ -524,6 +537,7 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
       }
     }
 
+    if (b == 0 && tid == 0) tk_ins += wall_clock64() - tk_mark;
     if (goal) c_best = goal_cost;
     if (end == END_TREE_FULL) status |= PAKR_S_TREE_FULL;
     if (end == END_ITER_CAP) status |= PAKR_S_ITER_CAP;
@@ -559,6 +573,9 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
     h->call_rounds = (int)rounds_done;
     h->call_solutions = c_sol;
     h->status = status | (n_sol > 0 ? PAKR_S_SOLVED : 0);
+    h->ticks_nn = tk_nn;
+    h->ticks_roll = tk_roll;
+    h->ticks_ins = tk_ins;
   }
 }
 

@@ -77,7 +77,8 @@ class Stats(C.Structure):
                 ("expansions", C.c_longlong), ("insertions", C.c_longlong),
                 ("nn_pairs", C.c_longlong), ("c_best", C.c_double), ("call_ms", C.c_double),
                 ("t_first_ms", C.c_double), ("t_last_ms", C.c_double), ("call_iters", C.c_int),
-                ("call_rounds", C.c_int), ("call_solutions", C.c_int), ("reserved", C.c_int)]
+                ("call_rounds", C.c_int), ("call_solutions", C.c_int), ("reserved", C.c_int),
+                ("nn_ms", C.c_double), ("rollout_ms", C.c_double), ("insert_ms", C.c_double)]
 
 
 class Solution(C.Structure):

@@ -47,7 +47,7 @@ int main(void) {
          sizeof(pakr_goal), sizeof(pakr_params), sizeof(pakr_stats), sizeof(pakr_solution));
   P(pakr_system, vnorm_max); P(pakr_scene, sph_r); P(pakr_params, cost_bound);
   P(pakr_params, seed); P(pakr_params, max_path_edges); P(pakr_stats, c_best);
-  P(pakr_stats, call_iters); P(pakr_solution, t_ms);
+  P(pakr_stats, call_iters); P(pakr_stats, insert_ms); P(pakr_solution, t_ms);
   return 0;
 }
 """
