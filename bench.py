@@ -76,6 +76,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--grid", type=int, default=0)
+    ap.add_argument("--wg-per-cu", type=int, default=0)
+    ap.add_argument("--lanes", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the planner has no "
@@ -91,7 +93,8 @@ def main():
     torch.cuda.set_device(0)
     dev_name = torch.cuda.get_device_name(0)
 
-    warm = [pakr.Plan(W.config_c2(seed=10_000 + i), grid=args.grid) for i in range(args.warmup)]
+    mk = lambda pr: pakr.Plan(pr, grid=args.grid, lanes=args.lanes, wg_per_cu=args.wg_per_cu)
+    warm = [mk(W.config_c2(seed=10_000 + i)) for i in range(args.warmup)]
     for p in warm:
         p.replan(budget_ms=args.budget_ms)
     torch.cuda.synchronize()
@@ -99,7 +102,7 @@ def main():
         p.close()
 
     probs = [W.config_c2(seed=s) for s in range(args.steps)]
-    plans = [pakr.Plan(pr, grid=args.grid) for pr in probs]
+    plans = [mk(pr) for pr in probs]
     stream = torch.cuda.current_stream()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in plans]
@@ -160,10 +163,15 @@ def main():
         "cost_final_median": med(c_final),
         "solved": f"{len(solved)}/{len(plans)}",
         "iterations_per_step": iters / len(plans),
+        "mean_tree_size": nn_pairs / max(iters, 1) / prob.K,
         "insertions_per_s": insertions / wall,
         "kernel_ms_mean": statistics.mean(kernel_ms),
         "phase_ms_per_step": {"nn": nn_ms / len(plans), "rollout": roll_ms / len(plans),
                               "insert": ins_ms / len(plans)},
+        "step_ms_per_step": dict(zip(["nn_scan", "barrier_a", "parent_reduce", "rollout",
+                                      "barrier_b", "insert"],
+                                     [sum(s["step_ms"][i] for s in stats) / len(plans)
+                                      for i in range(6)])),
         "nn_phase": {"tflops": nn_pairs * f_nn / (nn_ms / 1e3) / 1e12 if nn_ms else None,
                      "tree_read_gbs": nn_bytes / (nn_ms / 1e3) / 1e9 if nn_ms else None},
         "rollout_phase": {"tflops": expansions * f_exp / (roll_ms / 1e3) / 1e12 if roll_ms else None,

@@ -142,6 +142,10 @@ typedef struct pakr_params {
   int max_iters_per_round;         /* a round with no solution ends after this many     */
   int grid;                        /* workgroups of the persistent launch, 0 = auto     */
   int max_path_edges;              /* capacity of the stored best path, 0 = 4096        */
+  int lanes_per_candidate;         /* 1, 2, 4 or 8 lanes share one rollout and split its
+                                      obstacle tests; 0 = auto (from the obstacle count) */
+  int workgroups_per_cu;           /* with grid = 0: launch this many workgroups per CU
+                                      and reserve LDS so that no CU holds more; 0 = 1    */
 } pakr_params;
 
 typedef struct pakr_stats {
@@ -166,6 +170,9 @@ typedef struct pakr_stats {
   double nn_ms;                    /* last call, device time in SampleStates + NN       */
   double rollout_ms;               /* ... in controls, rollout, validity and prune      */
   double insert_ms;                /* ... in insertion, goal test and bookkeeping       */
+  double step_ms[6];               /* finer split, seen by workgroup 0: NN scan, wait at the
+                                      first grid barrier, parent reduction, rollout, wait at
+                                      the second barrier, insertion + bookkeeping        */
 } pakr_stats;
 
 typedef struct pakr_solution {

@@ -48,11 +48,25 @@ int sys_m(int id) {
 
 int obs_floats_of(int npos, int n_box, int n_sph) { return n_box * 2 * npos + n_sph * (npos + 1); }
 
-Layout make_layout(int d, int m, const pakr_params& p, int G, int obs_floats) {
+// Lanes per candidate: split the obstacle set so each lane tests about three
+// or more, as long as the rollout workgroups fit in the grid (and MAX_GR).
+int lanes_for(const pakr_params& p, int n_obs, int grid_limit) {
+  int L = p.lanes_per_candidate;
+  if (L <= 0) {
+    L = 1;
+    while (L < 8 && n_obs >= 3 * (2 * L)) L <<= 1;
+  }
+  const size_t cap = (size_t)std::min(grid_limit, MAX_GR);
+  while (L > 1 && ((size_t)p.B * L + NT - 1) / NT > cap) L >>= 1;
+  return L;
+}
+
+Layout make_layout(int d, int m, const pakr_params& p, int G, int obs_floats, int lanes) {
   Layout L{};
   const int K = p.B / p.A;
-  const int GR = (p.B + NT - 1) / NT;
-  const size_t S = (size_t)GR * NT;
+  const int cpb = NT / lanes;
+  const int GR = (p.B + cpb - 1) / cpb;
+  const size_t S = (size_t)GR * cpb;
   const int maxe = p.max_path_edges > 0 ? p.max_path_edges : DEFAULT_PATH_EDGES;
   const size_t N = (size_t)p.n_cap;
   size_t off = 0;
@@ -155,6 +169,10 @@ std::string validate(const pakr_system* s, const pakr_scene* sc, const float* x0
   if (p->max_iters_per_round < 1) return "max_iters_per_round must be >= 1";
   if (p->grid < 0) return "grid must be >= 0";
   if (p->max_path_edges < 0) return "max_path_edges must be >= 0";
+  if (p->lanes_per_candidate != 0 && p->lanes_per_candidate != 1 && p->lanes_per_candidate != 2 &&
+      p->lanes_per_candidate != 4 && p->lanes_per_candidate != 8)
+    return "lanes_per_candidate must be 0, 1, 2, 4 or 8";
+  if (p->workgroups_per_cu < 0 || p->workgroups_per_cu > 8) return "workgroups_per_cu must be 0..8";
   const int P = sc->npos;
   for (int c = 0; c < P; ++c)
     if (!finite_f(sc->ws_lo[c]) || !finite_f(sc->ws_hi[c]) || !(sc->ws_lo[c] < sc->ws_hi[c]))
@@ -251,9 +269,15 @@ size_t pakr_workspace_size(const pakr_system* sys, const pakr_params* params,
       params->n_cap < 1 || params->grid < 0)
     return 0;
   const int G = params->grid > 0 ? params->grid : AUTO_GRID_MAX;
-  const int of = obs_floats_of(sys_npos(sys->id), std::max(scene->n_box, 0),
-                               std::max(scene->n_sphere, 0));
-  return make_layout(d, m, *params, G, of).total;
+  const int nb = std::max(scene->n_box, 0), ns = std::max(scene->n_sphere, 0);
+  const int of = obs_floats_of(sys_npos(sys->id), nb, ns);
+  size_t worst = 0;  // the auto lane choice may differ; size for the largest layout
+  for (int lanes = 1; lanes <= 8; lanes <<= 1) {
+    pakr_params q = *params;
+    q.lanes_per_candidate = lanes;
+    worst = std::max(worst, make_layout(d, m, q, G, of, lanes).total);
+  }
+  return worst;
 }
 
 int pakr_plan_init(const pakr_system* sys, const pakr_scene* scene, const float* x_init,
@@ -291,11 +315,33 @@ int pakr_plan_init(const pakr_system* sys, const pakr_scene* scene, const float*
 
   const int d = sys->d, m = sys->m, P = scene->npos;
   const int K = params->B / params->A;
-  const int GR = (params->B + NT - 1) / NT;
   pl->qt = qt_for(K);
   pl->kfn = kernel_for(sys->id, pl->qt);
   const int of = obs_floats_of(P, scene->n_box, scene->n_sphere);
-  pl->shmem = sizeof(float) * (size_t)std::max(of, 1);
+  const size_t obs_bytes = sizeof(float) * (size_t)std::max(of, 1);
+  pl->shmem = obs_bytes;
+  int G = 0;
+  if (params->grid > 0) {
+    G = params->grid;
+  } else {
+    // k workgroups on every CU: reserve enough LDS that a CU cannot hold k+1,
+    // so the co-resident grid of k * CUs is spread evenly
+    const int k = params->workgroups_per_cu > 0 ? params->workgroups_per_cu : 1;
+    int lds_cu = 0, lds_max = 0;
+    hipFuncAttributes fa;
+    if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                              pl->device) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, pl->device) !=
+            hipSuccess ||
+        hipFuncGetAttributes(&fa, pl->kfn) != hipSuccess) {
+      delete pl;
+      return fail(nullptr, PAKR_E_HIP, "LDS attribute query failed");
+    }
+    const size_t want = (size_t)lds_cu / (size_t)(k + 1) + 1024;  // > LDS/(k+1) per workgroup
+    const size_t dyn = want > fa.sharedSizeBytes ? want - fa.sharedSizeBytes : 0;
+    if (dyn + fa.sharedSizeBytes <= (size_t)lds_max && dyn > obs_bytes) pl->shmem = dyn;
+    G = k * n_cu;
+  }
   int per_cu = 0;
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pl->kfn, NT, pl->shmem);
   if (e != hipSuccess || per_cu < 1) {
@@ -305,7 +351,11 @@ int pakr_plan_init(const pakr_system* sys, const pakr_scene* scene, const float*
     return rc;
   }
   const int max_coresident = per_cu * n_cu;
-  int G = params->grid > 0 ? params->grid : std::min(std::min(per_cu, 2) * n_cu, AUTO_GRID_MAX);
+  if (params->grid <= 0) G = std::min(G, max_coresident);
+  const int lanes = lanes_for(*params, scene->n_box + scene->n_sphere,
+                              params->grid > 0 ? G : max_coresident);
+  const int cpb = NT / lanes;
+  const int GR = (params->B + cpb - 1) / cpb;
   if (G < GR) G = params->grid > 0 ? -1 : GR;
   if (G < 1 || G > max_coresident) {
     char buf[160];
@@ -316,7 +366,7 @@ int pakr_plan_init(const pakr_system* sys, const pakr_scene* scene, const float*
   }
   pl->G = G;
 
-  pl->L = make_layout(d, m, *params, G, of);
+  pl->L = make_layout(d, m, *params, G, of, lanes);
   const size_t need = pl->L.total;
   if (d_workspace) {
     if (ws_bytes < need) {
@@ -358,6 +408,8 @@ int pakr_plan_init(const pakr_system* sys, const pakr_scene* scene, const float*
   Q.n_sph = scene->n_sphere;
   Q.G = G;
   Q.G_roll = GR;
+  Q.lanes = lanes;
+  Q.cpb = cpb;
   Q.max_path_edges = params->max_path_edges > 0 ? params->max_path_edges : DEFAULT_PATH_EDGES;
   Q.obs_floats = of;
   Q.key0 = (uint32_t)(params->seed & 0xffffffffull);
@@ -539,9 +591,10 @@ int pakr_status(pakr_plan* pl, pakr_stats* out) {
   out->call_iters = h.call_iters;
   out->call_rounds = h.call_rounds;
   out->call_solutions = h.call_solutions;
-  out->nn_ms = (double)h.ticks_nn / pl->ticks_per_ms;
-  out->rollout_ms = (double)h.ticks_roll / pl->ticks_per_ms;
-  out->insert_ms = (double)h.ticks_ins / pl->ticks_per_ms;
+  for (int i = 0; i < 6; ++i) out->step_ms[i] = (double)h.ticks[i] / pl->ticks_per_ms;
+  out->nn_ms = out->step_ms[0] + out->step_ms[1];
+  out->rollout_ms = out->step_ms[2] + out->step_ms[3] + out->step_ms[4];
+  out->insert_ms = out->step_ms[5];
   return PAKR_OK;
 }
 

@@ -10,9 +10,12 @@
 
 namespace pakr {
 
-constexpr int NT = 256;          // threads per workgroup (four wave64s)
+constexpr int NT = 512;          // threads per workgroup (eight wave64s)
+constexpr int TILE = 64;         // tree nodes per NN tile (unit of ownership)
 constexpr int WAVE = 64;
 constexpr int MAX_SOLUTIONS = 1024;
+constexpr int MAX_GR = 1024;     // rollout workgroups per iteration
+constexpr int VAL_FLOATS = 32;   // validity record held in LDS (see load_validity)
 
 enum : int { F_VALID = 1, F_PRUNE_OK = 2, F_KEEP = 4, F_GOAL = 8 };
 enum : int { END_NONE = 0, END_GOAL = 1, END_TREE_FULL = 2, END_ITER_CAP = 3 };
@@ -25,6 +28,7 @@ struct DevProblem {
   int n_cap, cost_kind, h_kind, max_iters_per_round;
   int n_box, n_sph, G, G_roll;
   int max_path_edges, obs_floats;
+  int lanes, cpb;                  // lanes per candidate, candidates per rollout workgroup
   uint32_t key0, key1;
   float dt, h_speed, c0, vnorm_max;
   float goal_r, goal_r2, edge_duration, pad0;
@@ -50,8 +54,7 @@ struct DevHeader {
   uint32_t release;                          // barrier release word
   int stop[2];                               // per-iteration stop decision (parity)
   int pad5;
-  long long ticks_nn, ticks_roll, ticks_ins; // per-phase device time of the last call
-  long long pad6;
+  long long ticks[8];                        // per-step device time of the last call
 };
 
 struct DevSolution {
@@ -127,10 +130,11 @@ __device__ __forceinline__ void sample_control(const DevProblem& P, uint32_t k, 
 // Systems.  Sizes are compile-time so every state lives in registers.
 // ---------------------------------------------------------------------------
 template <int SYS> struct Sys;
-template <> struct Sys<PAKR_DI2> { static constexpr int D = 4, M = 2, P = 2; };
-template <> struct Sys<PAKR_DI3> { static constexpr int D = 6, M = 3, P = 3; };
-template <> struct Sys<PAKR_CAR> { static constexpr int D = 5, M = 2, P = 2; };
-template <> struct Sys<PAKR_QUAD> { static constexpr int D = 12, M = 4, P = 3; };
+// D state dims, M controls, P position dims, CH steps per collision sweep.
+template <> struct Sys<PAKR_DI2> { static constexpr int D = 4, M = 2, P = 2, CH = 8; };
+template <> struct Sys<PAKR_DI3> { static constexpr int D = 6, M = 3, P = 3, CH = 8; };
+template <> struct Sys<PAKR_CAR> { static constexpr int D = 5, M = 2, P = 2, CH = 8; };
+template <> struct Sys<PAKR_QUAD> { static constexpr int D = 12, M = 4, P = 3, CH = 4; };
 
 // x' = f(x, u), Eq. (1).
 template <int SYS>
@@ -206,47 +210,83 @@ __device__ __forceinline__ void rk4_step(const DevProblem& P, float* x, const fl
   for (int i = 0; i < D; ++i) x[i] = x[i] + h6 * (k1[i] + 2.0f * (k2[i] + k3[i]) + k4[i]);
 }
 
-// Validity of one state: closed workspace, state limits, outside every closed
-// obstacle.  Obstacles sit in LDS: boxes first as (c[NP], h[NP]) records,
-// then spheres as (c[NP], r^2).  NaN compares false and so is invalid.
+// The validity constants of a query, copied to LDS once per launch:
+// [0,3) workspace lo, [3,6) workspace hi, [6,18) state lower limits,
+// [18,30) upper limits, [30] squared speed bound (+inf when none).
+__device__ __forceinline__ void load_validity(const DevProblem& P, float* s_val, int tid) {
+  if (tid < 3) {
+    s_val[tid] = P.ws_lo[tid];
+    s_val[3 + tid] = P.ws_hi[tid];
+  }
+  if (tid < PAKR_MAX_D) {
+    s_val[6 + tid] = P.lim_lo[tid];
+    s_val[18 + tid] = P.lim_hi[tid];
+  }
+  if (tid == 0) s_val[30] = P.vnorm_max > 0.0f ? P.vnorm_max * P.vnorm_max : INFINITY;
+}
+
+// Workspace box and state limits of one state (no obstacles); branch free.
+// NaN compares false and so is invalid.
 template <int SYS>
-__device__ __forceinline__ bool state_ok(const DevProblem& P, const float* x, const float* s_obs) {
+__device__ __forceinline__ bool limits_ok(const float* s_val, const float* x) {
   constexpr int D = Sys<SYS>::D, NP = Sys<SYS>::P;
   bool ok = true;
 #pragma unroll
-  for (int c = 0; c < NP; ++c) ok = ok && (x[c] >= P.ws_lo[c]) && (x[c] <= P.ws_hi[c]);
+  for (int c = 0; c < NP; ++c) ok = ok & (x[c] >= s_val[c]) & (x[c] <= s_val[3 + c]);
 #pragma unroll
-  for (int i = NP; i < D; ++i) ok = ok && (x[i] >= P.lim_lo[i]) && (x[i] <= P.lim_hi[i]);
+  for (int i = NP; i < D; ++i) ok = ok & (x[i] >= s_val[6 + i]) & (x[i] <= s_val[18 + i]);
   if constexpr (SYS == PAKR_DI2 || SYS == PAKR_DI3) {
-    if (P.vnorm_max > 0.0f) {
-      float s2 = 0.0f;
+    float s2 = 0.0f;
 #pragma unroll
-      for (int c = 0; c < NP; ++c) s2 += x[NP + c] * x[NP + c];
-      ok = ok && (s2 <= P.vnorm_max * P.vnorm_max);
-    }
+    for (int c = 0; c < NP; ++c) s2 += x[NP + c] * x[NP + c];
+    ok = ok & (s2 <= s_val[30]);
   }
+  return ok;
+}
+
+// True if any of CH positions lies in a closed obstacle.  Obstacles sit in
+// LDS: boxes first as (c[NP], h[NP]) records, then spheres as (c[NP], r^2).
+// This lane tests obstacles first, first + stride, ...; NaN coordinates
+// never hit (limits_ok rejects them).
+template <int NP, int CH>
+__device__ __forceinline__ bool any_obstacle_hit(const float (&pos)[CH][NP], const float* s_obs,
+                                                 int nb, int ns, int first, int stride) {
   bool hit = false;
-  const int nb = P.n_box;
-  for (int b = 0; b < nb; ++b) {
+  for (int b = first; b < nb; b += stride) {
     const float* o = s_obs + b * (2 * NP);
-    bool inside = true;
-#pragma unroll
-    for (int c = 0; c < NP; ++c) inside = inside && (fabsf(x[c] - o[c]) <= o[NP + c]);
-    hit = hit || inside;
-  }
-  const float* sp = s_obs + nb * (2 * NP);
-  const int ns = P.n_sph;
-  for (int s = 0; s < ns; ++s) {
-    const float* o = sp + s * (NP + 1);
-    float d2 = 0.0f;
+    float oc[NP], oh[NP];
 #pragma unroll
     for (int c = 0; c < NP; ++c) {
-      const float e = x[c] - o[c];
-      d2 += e * e;
+      oc[c] = o[c];
+      oh[c] = o[NP + c];
     }
-    hit = hit || (d2 <= o[NP]);
+#pragma unroll
+    for (int s = 0; s < CH; ++s) {
+      bool inside = true;
+#pragma unroll
+      for (int c = 0; c < NP; ++c) inside = inside & (fabsf(pos[s][c] - oc[c]) <= oh[c]);
+      hit = hit | inside;
+    }
   }
-  return ok && !hit;
+  const float* sp = s_obs + nb * (2 * NP);
+  for (int q = first; q < ns; q += stride) {
+    const float* o = sp + q * (NP + 1);
+    float oc[NP];
+#pragma unroll
+    for (int c = 0; c < NP; ++c) oc[c] = o[c];
+    const float r2 = o[NP];
+#pragma unroll
+    for (int s = 0; s < CH; ++s) {
+      float d2 = 0.0f;
+#pragma unroll
+      for (int c = 0; c < NP; ++c) {
+        const float e = pos[s][c] - oc[c];
+        d2 += e * e;
+      }
+      hit = hit | (d2 <= r2);
+    }
+  }
+  return hit;
 }
 
 template <int SYS>

@@ -5,7 +5,7 @@
 // separated by two grid barriers:
 //
 //   1. SampleStates + NearestNeighbor.  Every workgroup draws all K targets
-//      (Philox, registers) and scans the tree tiles it owns -- tile t (256
+//      (Philox, registers) and scans the tree tiles it owns -- tile t (64
 //      nodes) belongs to workgroup t mod G -- staging each tile through LDS and
 //      keeping a per-target (distance, index) minimum.  The partial minima go
 //      to HBM as packed u64 keys [G][K].
@@ -42,9 +42,9 @@ struct KArgs {
   float* actions;                   // [m][n_cap]
   int* parents;                     // [n_cap]
   float* costs;                     // [n_cap]
-  const float* obs;                 // packed obstacles (see state_ok)
+  const float* obs;                 // packed obstacles (see any_obstacle_hit)
   unsigned long long* partial;      // [G][K] packed (d2 bits << 32 | node)
-  float* stg;                       // survivor staging, S = G_roll*256 entries
+  float* stg;                       // survivor staging, S = G_roll*cpb entries
   int* counts;                      // [G_roll] survivors per rollout workgroup
   unsigned long long* goalmin;      // [G_roll] packed (cost bits << 32 | j)
   int* trace;                       // nullable: per-iteration records
@@ -141,16 +141,54 @@ struct TraceView {
   }
 };
 
+// Exclusive prefix sum of cnt[0..n) into off[0..n], off[n] = total; n <= 4*NT.
+// Every thread of the workgroup must call it; ends with a barrier.
+__device__ __forceinline__ void block_exclusive_scan(const int* cnt, int* off, int n, int* s_wave) {
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+  int v[4];
+  int sum = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int idx = tid * 4 + i;
+    v[i] = idx < n ? cnt[idx] : 0;
+    sum += v[i];
+  }
+  int incl = sum;  // inclusive scan of the per-thread sums within the wave
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const int t = __shfl_up(incl, o);
+    if (lane >= o) incl += t;
+  }
+  if (lane == WAVE - 1) s_wave[wv] = incl;
+  __syncthreads();
+  int wbase = 0, total = 0;
+#pragma unroll
+  for (int w = 0; w < NT / WAVE; ++w) {
+    wbase += (w < wv) ? s_wave[w] : 0;
+    total += s_wave[w];
+  }
+  int run = wbase + incl - sum;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int idx = tid * 4 + i;
+    if (idx < n) off[idx] = run;
+    run += v[i];
+  }
+  if (tid == 0) off[n] = total;
+  __syncthreads();
+}
+
 template <int SYS, int QT>
 __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
   constexpr int D = Sys<SYS>::D, M = Sys<SYS>::M, NP = Sys<SYS>::P;
   const DevProblem& P = a.P;
   extern __shared__ float s_obs[];
-  __shared__ float s_tile[D][NT];
+  __shared__ __align__(16) float s_tile[D][TILE];
   __shared__ unsigned long long s_best[NT];
-  __shared__ int s_cnt[NT + 1];
-  __shared__ int s_off[NT + 1];
+  __shared__ int s_cnt[MAX_GR];
+  __shared__ int s_off[MAX_GR + 1];
   __shared__ int s_wave[NT / WAVE];
+  __shared__ float s_val[VAL_FLOATS];
   __shared__ unsigned long long s_goal;
   __shared__ int s_fail;
   __shared__ int s_misc[2];
@@ -159,7 +197,8 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
   const int b = blockIdx.x;
   const int G = gridDim.x;
   const int B = P.B, A = P.A, K = P.K, GR = P.G_roll;
-  const int S = GR * NT;
+  const int L = P.lanes, CPB = P.cpb;   // lanes per candidate, candidates per rollout workgroup
+  const int S = GR * CPB;
   const size_t NC = (size_t)P.n_cap;
 
   float* stg_x = a.stg;
@@ -170,6 +209,7 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
   int* stg_f = stg_j + S;
 
   for (int i = tid; i < P.obs_floats; i += NT) s_obs[i] = a.obs[i];
+  load_validity(P, s_val, tid);
 
   // loop state: identical in every workgroup
   int n = a.hdr->n, round = a.hdr->round, iter = a.hdr->iter;
@@ -182,7 +222,17 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
   // workgroup-0 bookkeeping
   long long t0 = 0, deadline = LLONG_MAX, guard = LLONG_MAX, t_first = -1, t_last = -1;
   unsigned long long c_exp = 0, c_ins = 0, c_nn = 0;
-  long long tk_nn = 0, tk_roll = 0, tk_ins = 0, tk_mark = 0;
+  // workgroup 0 accumulates device time per step of the iteration:
+  // 0 NN scan, 1 wait at barrier A, 2 parent reduction, 3 rollout,
+  // 4 wait at barrier B, 5 insertion and bookkeeping
+  long long tk[6] = {0, 0, 0, 0, 0, 0}, tk_mark = 0;
+  auto mark = [&](int slot) {
+    if (b == 0 && tid == 0) {
+      const long long now = wall_clock64();
+      tk[slot] += now - tk_mark;
+      tk_mark = now;
+    }
+  };
   int c_sol = 0;
   if (b == 0) {
     t0 = wall_clock64();
@@ -196,7 +246,7 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
     if (a.max_rounds > 0 && rounds_done >= a.max_rounds) { status |= PAKR_S_ROUNDS_DONE; break; }
     int* trace = (a.trace != nullptr && it_done < a.trace_iters) ? a.trace + it_done * a.trace_words
                                                                  : nullptr;
-    const int ntiles = (n + NT - 1) / NT;
+    const int ntiles = (n + TILE - 1) / TILE;
     const int G_act = min(G, ntiles);
     if (b == 0 && tid == 0) tk_mark = wall_clock64();
 
@@ -223,30 +273,55 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
         }
       }
       if (b < G_act) {
-        for (int t = b; t < ntiles; t += G) {
-          const int node0 = t * NT;
-          const int len = min(NT, n - node0);
-          __syncthreads();
-          if (tid < len) {
+        // software pipeline: the next owned tile is fetched into registers
+        // while the current one is scanned from LDS.  Slots past the tree end
+        // get a coordinate whose squared distance overflows to +inf.
+        constexpr int PF = (D * TILE + NT - 1) / NT;
+        float pre[PF];
+        auto fetch = [&](int t) {
+          const int node0 = t * TILE;
 #pragma unroll
-            for (int c = 0; c < D; ++c) s_tile[c][tid] = a.states[(size_t)c * NC + node0 + tid];
+          for (int r = 0; r < PF; ++r) {
+            const int idx = tid + r * NT;
+            const int c = idx / TILE, i = idx - c * TILE;
+            pre[r] = (idx < D * TILE && node0 + i < n) ? a.states[(size_t)c * NC + node0 + i]
+                                                       : 3.0e38f;
+          }
+        };
+        fetch(b);
+        for (int t = b; t < ntiles; t += G) {
+          const int node0 = t * TILE;
+          __syncthreads();
+#pragma unroll
+          for (int r = 0; r < PF; ++r) {
+            const int idx = tid + r * NT;
+            if (idx < D * TILE) (&s_tile[0][0])[idx] = pre[r];
           }
           __syncthreads();
-          for (int i = 0; i < len; ++i) {
-            float pc[D];
+          if (t + G < ntiles) fetch(t + G);
+#pragma unroll 2
+          for (int i = 0; i < TILE; i += 4) {
+            float4 pc[D];
 #pragma unroll
-            for (int c = 0; c < D; ++c) pc[c] = s_tile[c][i];
+            for (int c = 0; c < D; ++c) pc[c] = *reinterpret_cast<const float4*>(&s_tile[c][i]);
 #pragma unroll
             for (int qq = 0; qq < QT; ++qq) {
-              float s = 0.0f;
+              float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
 #pragma unroll
               for (int c = 0; c < D; ++c) {
-                const float e = q[qq][c] - pc[c];
-                s = fmaf(e, e, s);
+                const float e0 = q[qq][c] - pc[c].x, e1 = q[qq][c] - pc[c].y;
+                const float e2 = q[qq][c] - pc[c].z, e3 = q[qq][c] - pc[c].w;
+                s0 = fmaf(e0, e0, s0);
+                s1 = fmaf(e1, e1, s1);
+                s2 = fmaf(e2, e2, s2);
+                s3 = fmaf(e3, e3, s3);
               }
-              if (s < bd[qq]) {
-                bd[qq] = s;
-                bi[qq] = node0 + i;
+              // only a strictly smaller distance replaces the best, and among
+              // equal ones the lowest node index wins (the sequential rule)
+              const float m = fminf(fminf(s0, s1), fminf(s2, s3));
+              if (m < bd[qq]) {
+                bd[qq] = m;
+                bi[qq] = node0 + i + (s0 == m ? 0 : (s1 == m ? 1 : (s2 == m ? 2 : 3)));
               }
             }
           }
@@ -258,6 +333,7 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
         }
       }
     }
+    mark(0);
     if (b == 0 && tid == 0) {
       const long long now = wall_clock64();
       const int stop = now >= deadline ? 1 : (now >= guard ? 2 : 0);
@@ -276,35 +352,61 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
       status |= (s_misc[0] == 1) ? PAKR_S_BUDGET_EXPIRED : PAKR_S_DEVICE_ERROR;
       break;
     }
-    if (b == 0 && tid == 0) {
-      const long long now = wall_clock64();
-      tk_nn += now - tk_mark;
-      tk_mark = now;
-    }
+    mark(1);
 
     // ---------------- phase 2: controls, rollout, validity, prune ---------
     if (b < GR) {
-      const int j0 = b * NT;
-      const int j1 = min(B, j0 + NT);
+      const int j0 = b * CPB;
+      const int j1 = min(B, j0 + CPB);
       const int k0 = j0 / A;
       const int nql = (j1 - 1) / A - k0 + 1;
       for (int i = tid; i < nql; i += NT) s_best[i] = ~0ull;
       if (tid == 0) s_goal = ~0ull;
       __syncthreads();
-      const int tot = nql * G_act;
-      for (int idx = tid; idx < tot; idx += NT) {
-        const int qi = idx % nql;
-        const int src = idx / nql;
-        atomicMin(&s_best[qi], a.partial[(size_t)src * K + k0 + qi]);
+      if (NT % nql == 0) {
+        // each thread folds a strided set of workgroups' keys for one target
+        // in registers (independent loads in flight), then one LDS atomic
+        const int qi = tid % nql, stride = NT / nql;
+        const unsigned long long* src_p = a.partial + k0 + qi;
+        unsigned long long m0 = ~0ull, m1 = ~0ull;
+        int src = tid / nql;
+        for (; src + 7 * stride < G_act; src += 8 * stride) {
+          unsigned long long v[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) v[u] = src_p[(size_t)(src + u * stride) * K];
+#pragma unroll
+          for (int u = 0; u < 8; u += 2) {
+            m0 = v[u] < m0 ? v[u] : m0;
+            m1 = v[u + 1] < m1 ? v[u + 1] : m1;
+          }
+        }
+        for (; src < G_act; src += stride) {
+          const unsigned long long v = src_p[(size_t)src * K];
+          m0 = v < m0 ? v : m0;
+        }
+        m0 = m1 < m0 ? m1 : m0;
+        if (m0 != ~0ull) atomicMin(&s_best[qi], m0);
+      } else {
+        const int tot = nql * G_act;
+        for (int idx = tid; idx < tot; idx += NT) {
+          const int qi = idx % nql;
+          const int src = idx / nql;
+          atomicMin(&s_best[qi], a.partial[(size_t)src * K + k0 + qi]);
+        }
       }
       __syncthreads();
+      mark(2);
 
-      const int j = j0 + tid;
+      // L consecutive lanes share candidate j: each integrates the edge and
+      // tests every L-th obstacle; the group ORs its hits
+      const int lg = tid % L;
+      const int j = j0 + tid / L;
       const bool active = j < B;
       float x[D], u[M];
       float cost = 0.0f;
       bool valid = false, prune_ok = false, in_goal = false;
       int parent = 0, k = 0, br = 0;
+      bool hit = false;
       if (active) {
         k = j / A;
         br = j - k * A;
@@ -313,31 +415,48 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
 #pragma unroll
         for (int c = 0; c < D; ++c) x[c] = a.states[(size_t)c * NC + parent];
         const float c_par = a.costs[parent];
-        valid = true;
         float len = 0.0f;
         const bool path_len = P.cost_kind == PAKR_COST_PATH_LENGTH;
-        for (int t = 0; t < P.T; ++t) {
-          float xp[NP];
+        constexpr int CH = Sys<SYS>::CH;
+        bool lim_ok = true;
+        // integrate CH steps, then test their CH positions against this
+        // lane's obstacles in one sweep (each obstacle read once per chunk)
+        for (int t0 = 0; t0 < P.T; t0 += CH) {
+          float pos[CH][NP];
 #pragma unroll
-          for (int c = 0; c < NP; ++c) xp[c] = x[c];
-          rk4_step<SYS>(P, x, u, P.dt);
-          if (path_len) {
-            float s2 = 0.0f;
+          for (int s = 0; s < CH; ++s) {
+            if (t0 + s < P.T) {
+              float xp[NP];
 #pragma unroll
-            for (int c = 0; c < NP; ++c) {
-              const float e = x[c] - xp[c];
-              s2 += e * e;
+              for (int c = 0; c < NP; ++c) xp[c] = x[c];
+              rk4_step<SYS>(P, x, u, P.dt);
+              if (path_len) {
+                float s2 = 0.0f;
+#pragma unroll
+                for (int c = 0; c < NP; ++c) {
+                  const float e = x[c] - xp[c];
+                  s2 += e * e;
+                }
+                len += sqrtf(s2);
+              }
+              lim_ok = lim_ok & limits_ok<SYS>(s_val, x);
             }
-            len += sqrtf(s2);
+#pragma unroll
+            for (int c = 0; c < NP; ++c) pos[s][c] = x[c];  // past T: repeats the last state
           }
-          valid = state_ok<SYS>(P, x, s_obs) && valid;
+          hit = hit | any_obstacle_hit<NP, CH>(pos, s_obs, P.n_box, P.n_sph, lg, L);
         }
+        hit = hit | !lim_ok;
         cost = c_par + (path_len ? len : P.edge_duration);
         const float dist = sqrtf(goal_dist2<SYS>(P, x));
         prune_ok = (cost + heuristic<SYS>(P, dist)) < c_best;
         in_goal = dist <= P.goal_r;
       }
-      const bool keep = active && valid && prune_ok;
+      int hi = hit ? 1 : 0;
+      for (int o = 1; o < L; o <<= 1) hi |= __shfl_xor(hi, o);
+      valid = active && hi == 0;
+      const bool lead = lg == 0;
+      const bool keep = lead && active && valid && prune_ok;
       const unsigned long long mask = __ballot(keep);
       const int lane = tid & (WAVE - 1), wv = tid / WAVE;
       const int wrank = __popcll(mask & ((1ull << lane) - 1ull));
@@ -350,7 +469,7 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
         total += s_wave[w];
       }
       if (keep) {
-        const int e = b * NT + base_r + wrank;
+        const int e = b * CPB + base_r + wrank;
 #pragma unroll
         for (int c = 0; c < D; ++c) stg_x[(size_t)c * S + e] = x[c];
 #pragma unroll
@@ -366,7 +485,7 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
         a.counts[b] = total;
         a.goalmin[b] = s_goal;
       }
-      if (trace != nullptr && active) {
+      if (trace != nullptr && active && lead) {
         TraceView tv(trace, K, B, D, M);
         if (br == 0) tv.parents[k] = parent;
 #pragma unroll
@@ -379,38 +498,29 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
         tv.slots[j] = -1;
       }
     }
+    mark(3);
     if (!grid_barrier(a, gen, &s_fail)) {
       if (tid == 0) __hip_atomic_store(&a.hdr->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return;
     }
 
-    if (b == 0 && tid == 0) {
-      const long long now = wall_clock64();
-      tk_roll += now - tk_mark;
-      tk_mark = now;
-    }
+    mark(4);
 
     // ---------------- phase 3: insert + goal + round bookkeeping ----------
-    if (tid < GR) s_cnt[tid] = a.counts[tid];
+    for (int w = tid; w < GR; w += NT) s_cnt[w] = a.counts[w];
     __syncthreads();
-    if (tid == 0) {
-      int acc = 0;
-      for (int w = 0; w < GR; ++w) {
-        s_off[w] = acc;
-        acc += s_cnt[w];
-      }
-      s_off[GR] = acc;
-    }
-    __syncthreads();
+    block_exclusive_scan(s_cnt, s_off, GR, s_wave);
     const int survivors = s_off[GR];
     const int n0 = n;
     const int n_ins = min(survivors, P.n_cap - n0);
     const int n1 = n0 + n_ins;
     if (n_ins > 0) {
-      const int t_lo = n0 / NT, t_hi = (n1 - 1) / NT;
-      int t = t_lo + ((b - t_lo % G) % G + G) % G;
-      for (; t <= t_hi; t += G) {
-        const int s = t * NT + tid;
+      // this workgroup owns tiles t = b (mod G); copy the survivors that land there
+      const int t_lo = n0 / TILE, t_hi = (n1 - 1) / TILE;
+      const int t_first = t_lo + ((b - t_lo % G) % G + G) % G;
+      const int n_my = t_first <= t_hi ? (t_hi - t_first) / G + 1 : 0;
+      for (int idx = tid; idx < n_my * TILE; idx += NT) {
+        const int s = (t_first + (idx / TILE) * G) * TILE + (idx % TILE);
         if (s >= n0 && s < n1) {
           const int r = s - n0;
           int lo = 0, hi = GR - 1;
@@ -418,7 +528,7 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
             const int mid = (lo + hi + 1) >> 1;
             if (s_off[mid] <= r) lo = mid; else hi = mid - 1;
           }
-          const int e = lo * NT + (r - s_off[lo]);
+          const int e = lo * CPB + (r - s_off[lo]);
 #pragma unroll
           for (int c = 0; c < D; ++c) a.states[(size_t)c * NC + s] = stg_x[(size_t)c * S + e];
 #pragma unroll
@@ -434,13 +544,14 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
     }
     // cheapest inserted goal candidate, ties to the lowest j
     unsigned long long key = ~0ull;
-    if (tid < GR) {
-      const int off = s_off[tid], cnt = s_cnt[tid];
+    for (int w = tid; w < GR; w += NT) {
+      const int off = s_off[w], cnt = s_cnt[w];
       if (off + cnt <= n_ins) {
-        key = a.goalmin[tid];
+        const unsigned long long kk = a.goalmin[w];
+        key = kk < key ? kk : key;
       } else if (off < n_ins) {
         for (int l = 0; l < n_ins - off; ++l) {
-          const int e = tid * NT + l;
+          const int e = w * CPB + l;
           if (stg_f[e] & F_GOAL) {
             const unsigned long long kk = pack_key(stg_c[e], (uint32_t)stg_j[e]);
             key = kk < key ? kk : key;
@@ -462,10 +573,10 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
     if (goal) {
       goal_j = (int)(uint32_t)(gk & 0xffffffffull);
       goal_cost = __uint_as_float((uint32_t)(gk >> 32));
-      const int wg = goal_j / NT;
-      if (tid < s_cnt[wg] && stg_j[wg * NT + tid] == goal_j) s_misc[1] = tid;
+      const int wg = goal_j / CPB;
+      if (tid < s_cnt[wg] && stg_j[wg * CPB + tid] == goal_j) s_misc[1] = tid;
       __syncthreads();
-      goal_e = wg * NT + s_misc[1];
+      goal_e = wg * CPB + s_misc[1];
       goal_slot = n0 + s_off[wg] + s_misc[1];
     }
     int end = END_NONE;
@@ -537,7 +648,7 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
       }
     }
 
-    if (b == 0 && tid == 0) tk_ins += wall_clock64() - tk_mark;
+    mark(5);
     if (goal) c_best = goal_cost;
     if (end == END_TREE_FULL) status |= PAKR_S_TREE_FULL;
     if (end == END_ITER_CAP) status |= PAKR_S_ITER_CAP;
@@ -573,9 +684,7 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
     h->call_rounds = (int)rounds_done;
     h->call_solutions = c_sol;
     h->status = status | (n_sol > 0 ? PAKR_S_SOLVED : 0);
-    h->ticks_nn = tk_nn;
-    h->ticks_roll = tk_roll;
-    h->ticks_ins = tk_ins;
+    for (int i = 0; i < 6; ++i) h->ticks[i] = tk[i];
   }
 }
 

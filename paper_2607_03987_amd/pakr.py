@@ -68,7 +68,8 @@ class Params(C.Structure):
                 ("n_cap", C.c_int), ("cost_kind", C.c_int), ("heuristic_kind", C.c_int),
                 ("h_speed", C.c_float), ("cost_bound", C.c_double), ("seed", C.c_uint64),
                 ("query_id", C.c_uint32), ("max_iters_per_round", C.c_int), ("grid", C.c_int),
-                ("max_path_edges", C.c_int)]
+                ("max_path_edges", C.c_int), ("lanes_per_candidate", C.c_int),
+                ("workgroups_per_cu", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -78,7 +79,8 @@ class Stats(C.Structure):
                 ("nn_pairs", C.c_longlong), ("c_best", C.c_double), ("call_ms", C.c_double),
                 ("t_first_ms", C.c_double), ("t_last_ms", C.c_double), ("call_iters", C.c_int),
                 ("call_rounds", C.c_int), ("call_solutions", C.c_int), ("reserved", C.c_int),
-                ("nn_ms", C.c_double), ("rollout_ms", C.c_double), ("insert_ms", C.c_double)]
+                ("nn_ms", C.c_double), ("rollout_ms", C.c_double), ("insert_ms", C.c_double),
+                ("step_ms", C.c_double * 6)]
 
 
 class Solution(C.Structure):
@@ -138,7 +140,8 @@ def _fp(a):
 class CQuery:
     """The C structs of one Problem (holds the host arrays alive)."""
 
-    def __init__(self, prob: W.Problem, grid: int = 0, max_path_edges: int = 0):
+    def __init__(self, prob: W.Problem, grid: int = 0, max_path_edges: int = 0, lanes: int = 0,
+                 wg_per_cu: int = 0):
         self.prob = prob
         s = System()
         s.id, s.d, s.m = prob.system, prob.d, prob.m
@@ -176,6 +179,8 @@ class CQuery:
         p.seed, p.query_id = int(prob.seed), int(prob.qid)
         p.max_iters_per_round = int(prob.max_iters_per_round)
         p.grid, p.max_path_edges = int(grid), int(max_path_edges)
+        p.lanes_per_candidate = int(lanes)
+        p.workgroups_per_cu = int(wg_per_cu)
         self.params = p
 
 
@@ -205,14 +210,16 @@ class Plan:
     calls are enqueued on torch's current stream.
     """
 
-    def __init__(self, prob: W.Problem, grid: int = 0, max_path_edges: int = 0, device=None):
+    def __init__(self, prob: W.Problem, grid: int = 0, max_path_edges: int = 0, device=None,
+                 lanes: int = 0, wg_per_cu: int = 0):
         import torch
 
         if not torch.cuda.is_available():
             raise RuntimeError("libpakr needs a ROCm GPU; none is visible")
         self.torch = torch
         self.prob = prob
-        self.q = CQuery(prob, grid=grid, max_path_edges=max_path_edges)
+        self.q = CQuery(prob, grid=grid, max_path_edges=max_path_edges, lanes=lanes,
+                        wg_per_cu=wg_per_cu)
         self.device = torch.device(device or "cuda")
         nbytes = workspace_size(self.q)
         if nbytes == 0:
@@ -260,7 +267,9 @@ class Plan:
     def status(self) -> dict:
         s = Stats()
         _check(load().pakr_status(self.h, C.byref(s)), self.h)
-        return {f[0]: getattr(s, f[0]) for f in Stats._fields_}
+        out = {f[0]: getattr(s, f[0]) for f in Stats._fields_}
+        out["step_ms"] = list(out["step_ms"])
+        return out
 
     def solutions(self) -> list:
         n = C.c_int(0)

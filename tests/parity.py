@@ -54,9 +54,9 @@ def compare_iteration(prob, tr, rep, ctx=""):
                 max_state_err=float(rel_err(tr["xnew"][ov], rep.xnew[ov]).max()) if ov.any() else 0.0)
 
 
-def step_parity(prob, n_iters, grid=0, log=None):
+def step_parity(prob, n_iters, grid=0, log=None, lanes=0):
     """Run n_iters GPU iterations one at a time; replay each in the reference."""
-    plan = pakr.Plan(prob, grid=grid)
+    plan = pakr.Plan(prob, grid=grid, lanes=lanes)
     orc = oracle.OraclePlan(prob)
     stats = []
     c_best = float(prob.c0)

@@ -46,8 +46,8 @@ int main(void) {
          "pakr_stats %zu\npakr_solution %zu\n", sizeof(pakr_system), sizeof(pakr_scene),
          sizeof(pakr_goal), sizeof(pakr_params), sizeof(pakr_stats), sizeof(pakr_solution));
   P(pakr_system, vnorm_max); P(pakr_scene, sph_r); P(pakr_params, cost_bound);
-  P(pakr_params, seed); P(pakr_params, max_path_edges); P(pakr_stats, c_best);
-  P(pakr_stats, call_iters); P(pakr_stats, insert_ms); P(pakr_solution, t_ms);
+  P(pakr_params, seed); P(pakr_params, max_path_edges); P(pakr_params, lanes_per_candidate); P(pakr_params, workgroups_per_cu); P(pakr_stats, c_best);
+  P(pakr_stats, call_iters); P(pakr_stats, insert_ms); P(pakr_stats, step_ms); P(pakr_solution, t_ms);
   return 0;
 }
 """

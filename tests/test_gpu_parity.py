@@ -53,6 +53,15 @@ def test_step_parity_no_obstacles_and_small_grid():
     step_parity(prob, 8, grid=8, log=_log)
 
 
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8])
+@pytest.mark.parametrize("cfg,kw", [("c2", dict(B=1024, A=8, n_cap=30000)),
+                                    ("c4", dict(B=256, A=16, n_cap=30000))])
+def test_step_parity_lanes_per_candidate(cfg, kw, lanes):
+    prob = W.CONFIGS[cfg](**kw)
+    print(f"case {prob.name} lanes {lanes}", flush=True)
+    step_parity(prob, 6, lanes=lanes, log=_log)
+
+
 def test_expand_in_pieces_equals_one_call():
     prob = W.config_c1()
     a = pakr.Plan(prob)
@@ -68,16 +77,18 @@ def test_expand_in_pieces_equals_one_call():
         np.testing.assert_array_equal(x, y)
 
 
-def test_replan_is_deterministic_and_grid_independent():
+def test_replan_is_deterministic_and_launch_shape_independent():
+    """Neither the grid size nor the lanes per candidate may change any result."""
     prob = W.config_c1(max_iters_per_round=80)
     res = []
-    for grid in (0, 4, 1):
-        p = pakr.Plan(prob, grid=grid)
+    for grid, lanes in ((0, 0), (0, 0), (4, 1), (1, 1), (8, 8), (3, 2)):
+        p = pakr.Plan(prob, grid=grid, lanes=lanes)
         p.replan(max_rounds=3)
         st = p.status()
         res.append((st["total_iters"], st["insertions"], [s["cost"] for s in p.solutions()],
                     p.copy_tree()))
-        print(f"grid {grid}: {st['total_iters']} iters, {len(res[-1][2])} solutions", flush=True)
+        print(f"grid {grid} lanes {lanes}: {st['total_iters']} iters, {len(res[-1][2])} "
+              f"solutions", flush=True)
     for r in res[1:]:
         assert r[0] == res[0][0] and r[1] == res[0][1] and r[2] == res[0][2]
         for x, y in zip(r[3], res[0][3]):
