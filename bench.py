@@ -50,6 +50,40 @@ def nn_flops_per_pair(prob):
     return 3 * prob.d
 
 
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_plan_di3_aox200ms_hbm_counters.md")
+KERNEL_SOURCES = ["paper_2607_03987_amd/csrc/pakr.hip", "paper_2607_03987_amd/csrc/pakr_device.hpp",
+                  "paper_2607_03987_amd/csrc/pakr_kernels.hpp", "include/pakr.h"]
+
+
+def measured_traffic():
+    """HBM bytes per planner launch from the committed rocprofv3 counter runs.
+
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled by the factors the
+    same counters gave for a known-size copy; None once the kernel sources no
+    longer hash to the profiled ones.
+    """
+    import hashlib
+    try:
+        txt = open(PMC_SUMMARY).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in txt.splitlines():
+        if ":" in line and line.split(":")[0] in ("fetch_factor", "write_factor",
+                                                  "fetch_kib_per_dispatch",
+                                                  "write_kib_per_dispatch", "source_sha256"):
+            k, v = line.split(":", 1)
+            vals[k] = v.split()[0]
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if vals.get("source_sha256") != h.hexdigest():
+        return None
+    return 1024.0 * (float(vals["fetch_kib_per_dispatch"]) * float(vals["fetch_factor"]) +
+                     float(vals["write_kib_per_dispatch"]) * float(vals["write_factor"]))
+
+
 def cpu_baseline(prob, seconds):
     """Time the FP64 reference (single thread) on the same query for ~`seconds`."""
     import oracle
@@ -78,6 +112,9 @@ def main():
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--wg-per-cu", type=int, default=0)
     ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="before timing, run one plain device copy of this size (a known-size "
+                         "kernel against which HBM counters are scaled)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the planner has no "
@@ -92,6 +129,14 @@ def main():
         _build.build(force=True)
     torch.cuda.set_device(0)
     dev_name = torch.cuda.get_device_name(0)
+    if args.calibrate_copy_mib > 0:
+        n = args.calibrate_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     mk = lambda pr: pakr.Plan(pr, grid=args.grid, lanes=args.lanes, wg_per_cu=args.wg_per_cu)
     warm = [mk(W.config_c2(seed=10_000 + i)) for i in range(args.warmup)]
@@ -178,7 +223,8 @@ def main():
                           "flops_per_expansion": f_exp},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
-                     "traffic": None, "kernel": "k_plan<DI3> (persistent AO-x planner)"},
+                     "traffic": measured_traffic(),
+                     "kernel": "k_plan<DI3> (persistent AO-x planner), one launch per query"},
         "cpu_baseline": None,
         "batched": None,
     }
