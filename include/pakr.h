@@ -173,6 +173,8 @@ typedef struct pakr_stats {
   double step_ms[6];               /* finer split, seen by workgroup 0: NN scan, wait at the
                                       first grid barrier, parent reduction, rollout, wait at
                                       the second barrier, insertion + bookkeeping        */
+  double clock_start_ms;           /* device clock (ms) when the last call started this query */
+  double clock_end_ms;             /* ... and when it finished it                        */
 } pakr_stats;
 
 typedef struct pakr_solution {
@@ -251,8 +253,58 @@ int pakr_copy_tree(pakr_plan* plan, float* states, float* actions, int* parents,
                    int n_max, int* n);
 
 /* Message for the last error of `plan` (or of the last failed
- * pakr_plan_init when plan is NULL).  Valid until the next call. */
+ * pakr_plan_init / pakr_batch_init when plan is NULL).  Valid until the next
+ * call. */
 const char* pakr_last_error(const pakr_plan* plan);
+
+/* ---------------------------------------------------------------------------
+ * Batched planning: many independent queries (mixed systems, uneven tree
+ * capacities) in one persistent launch.  Each workgroup takes the next query
+ * from a device work queue and runs that query's AO-x loop alone (the same
+ * iteration as a single-query plan, so every query's results are identical to
+ * planning it alone with the same parameters), then takes the next.
+ * ------------------------------------------------------------------------- */
+typedef struct pakr_batch pakr_batch;
+
+/* Device bytes for n queries (arrays of n entries, host).  0 if invalid. */
+size_t pakr_batch_workspace_size(int n, const pakr_system* sys, const pakr_scene* scenes,
+                                 const pakr_params* params);
+
+/* Validate and set up n queries: query q uses sys[q], scenes[q], x_inits[q]
+ * (host pointer to d floats), goals[q], params[q] (grid and
+ * workgroups_per_cu are ignored; lanes_per_candidate 0 means 1 here).  The
+ * workspace rules are those of pakr_plan_init.  On a validation error the
+ * message names the query.  Enqueues on `stream`. */
+int pakr_batch_init(int n, const pakr_system* sys, const pakr_scene* scenes,
+                    const float* const* x_inits, const pakr_goal* goals,
+                    const pakr_params* params, void* d_workspace, size_t ws_bytes, void* stream,
+                    pakr_batch** out);
+
+/* One launch: every query runs its AO-x loop under the same limits as
+ * pakr_replan (budget measured from the moment its workgroup starts it).
+ * Async. */
+int pakr_batch_replan(pakr_batch* batch, double budget_ms, int max_rounds, long long max_iters);
+
+/* Capture (work-queue reset + batch launch with these limits) into a
+ * hipGraph, replayed by pakr_batch_graph_launch on the batch's stream.
+ * Captured on an internal stream; replaces any earlier capture.  Syncs. */
+int pakr_batch_graph_capture(pakr_batch* batch, double budget_ms, int max_rounds,
+                             long long max_iters);
+int pakr_batch_graph_launch(pakr_batch* batch);
+
+/* Per-query results (sync); same meaning as the single-query calls. */
+int pakr_batch_status(pakr_batch* batch, int q, pakr_stats* out);
+int pakr_batch_solutions(pakr_batch* batch, int q, pakr_solution* out, int cap, int* n_total);
+int pakr_batch_extract_path(pakr_batch* batch, int q, float* states, float* actions,
+                            int cap_edges, int* n_edges, double* cost);
+
+/* Workgroups of the batch launch (queries run concurrently). */
+int pakr_batch_grid(const pakr_batch* batch);
+
+/* Message for the last error of `batch`. */
+const char* pakr_batch_last_error(const pakr_batch* batch);
+
+void pakr_batch_destroy(pakr_batch* batch);
 
 /* Static name of an error code. */
 const char* pakr_error_string(int code);

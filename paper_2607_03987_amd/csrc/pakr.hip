@@ -7,6 +7,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "pakr_kernels.hpp"
 
@@ -200,8 +201,6 @@ std::string validate(const pakr_system* s, const pakr_scene* sc, const float* x0
   return std::string();
 }
 
-typedef void (*kernel_fn)(KArgs);
-
 template <int SYS>
 const void* pick_kernel(int qt) {
   if (qt == 1) return reinterpret_cast<const void*>(&k_plan<SYS, 1>);
@@ -218,28 +217,254 @@ const void* kernel_for(int sys, int qt) {
   }
 }
 
+int qt_for(int K) { return K <= NT ? 1 : (K <= 2 * NT ? 2 : 4); }
+
+// The device record of one query planned by G workgroups with L lanes per candidate.
+DevProblem make_problem(const pakr_system& sys, const pakr_scene& scene, const pakr_goal& goal,
+                        const pakr_params& prm, int G, int lanes) {
+  DevProblem Q;
+  std::memset(&Q, 0, sizeof Q);
+  const int P = scene.npos;
+  Q.system = sys.id;
+  Q.d = sys.d;
+  Q.m = sys.m;
+  Q.npos = P;
+  Q.B = prm.B;
+  Q.A = prm.A;
+  Q.K = prm.B / prm.A;
+  Q.T = prm.T;
+  Q.n_cap = prm.n_cap;
+  Q.cost_kind = prm.cost_kind;
+  Q.h_kind = prm.heuristic_kind;
+  Q.max_iters_per_round = prm.max_iters_per_round;
+  Q.n_box = scene.n_box;
+  Q.n_sph = scene.n_sphere;
+  Q.G = G;
+  Q.lanes = lanes;
+  Q.cpb = NT / lanes;
+  Q.G_roll = (prm.B + Q.cpb - 1) / Q.cpb;
+  Q.max_path_edges = prm.max_path_edges > 0 ? prm.max_path_edges : DEFAULT_PATH_EDGES;
+  Q.obs_floats = obs_floats_of(P, scene.n_box, scene.n_sphere);
+  Q.key0 = (uint32_t)(prm.seed & 0xffffffffull);
+  Q.key1 = prm.query_id;
+  Q.dt = prm.dt;
+  Q.h_speed = prm.h_speed;
+  Q.c0 = (float)prm.cost_bound;
+  Q.vnorm_max = sys.vnorm_max;
+  Q.goal_r = goal.radius;
+  Q.goal_r2 = goal.radius * goal.radius;
+  {
+    volatile float tf = (float)prm.T;
+    volatile float ed = tf * prm.dt;  // one float32 rounding
+    Q.edge_duration = ed;
+  }
+  for (int i = 0; i < 8; ++i) Q.dyn[i] = sys.dyn[i];
+  for (int i = 0; i < PAKR_MAX_D; ++i) {
+    Q.sample_lo[i] = sys.sample_lo[i];
+    Q.sample_hi[i] = sys.sample_hi[i];
+    Q.lim_lo[i] = sys.lim_lo[i];
+    Q.lim_hi[i] = sys.lim_hi[i];
+  }
+  for (int i = 0; i < PAKR_MAX_M; ++i) {
+    Q.u_lo[i] = sys.u_lo[i];
+    Q.u_hi[i] = sys.u_hi[i];
+  }
+  for (int c = 0; c < 3; ++c) {
+    Q.ws_lo[c] = c < P ? scene.ws_lo[c] : 0.0f;
+    Q.ws_hi[c] = c < P ? scene.ws_hi[c] : 0.0f;
+    Q.goal_c[c] = c < P ? goal.center[c] : 0.0f;
+  }
+  return Q;
+}
+
+// Obstacles as the kernels read them: boxes (c[P], h[P]), then spheres (c[P], r^2).
+std::vector<float> pack_obstacles(const pakr_scene& sc) {
+  const int P = sc.npos;
+  std::vector<float> o;
+  o.reserve((size_t)std::max(obs_floats_of(P, sc.n_box, sc.n_sphere), 1));
+  for (int b = 0; b < sc.n_box; ++b) {
+    for (int c = 0; c < P; ++c) o.push_back(sc.box_c[b * P + c]);
+    for (int c = 0; c < P; ++c) o.push_back(sc.box_h[b * P + c]);
+  }
+  for (int q = 0; q < sc.n_sphere; ++q) {
+    for (int c = 0; c < P; ++c) o.push_back(sc.sph_c[q * P + c]);
+    o.push_back(sc.sph_r[q] * sc.sph_r[q]);
+  }
+  return o;
+}
+
+// Kernel arguments of a query whose buffers start at `base` with layout L.
+KArgs make_args(const DevProblem& Q, char* base, const Layout& L) {
+  KArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.P = Q;
+  a.hdr = reinterpret_cast<DevHeader*>(base + L.hdr);
+  a.bar_flags = reinterpret_cast<uint32_t*>(base + L.bar);
+  a.sols = reinterpret_cast<DevSolution*>(base + L.sols);
+  a.path_states = reinterpret_cast<float*>(base + L.pstates);
+  a.path_actions = reinterpret_cast<float*>(base + L.pactions);
+  a.states = reinterpret_cast<float*>(base + L.states);
+  a.actions = reinterpret_cast<float*>(base + L.actions);
+  a.parents = reinterpret_cast<int*>(base + L.parents);
+  a.costs = reinterpret_cast<float*>(base + L.costs);
+  a.obs = reinterpret_cast<const float*>(base + L.obs);
+  a.partial = reinterpret_cast<unsigned long long*>(base + L.partial);
+  a.stg = reinterpret_cast<float*>(base + L.stg);
+  a.counts = reinterpret_cast<int*>(base + L.counts);
+  a.goalmin = reinterpret_cast<unsigned long long*>(base + L.goalmin);
+  return a;
+}
+
+void set_limits(KArgs& a, long long max_iters, long long max_rounds, double budget_ms,
+                double ticks_per_ms) {
+  a.max_iters = max_iters;
+  a.max_rounds = max_rounds;
+  a.budget_ticks = budget_ms > 0 ? (long long)(budget_ms * ticks_per_ms) : 0;
+  const double guard_ms = (budget_ms > 0 ? budget_ms : 0.0) + 60000.0;
+  a.guard_ticks = (long long)(guard_ms * ticks_per_ms);
+  a.barrier_timeout_ticks = (long long)(2000.0 * ticks_per_ms);
+}
+
+// Copy the obstacles and enqueue the root write of one query.
+hipError_t upload_query(const KArgs& a, const std::vector<float>& obs, const float* x_init,
+                        int n_flags, hipStream_t stream) {
+  hipError_t e = hipSuccess;
+  if (!obs.empty()) {
+    e = hipMemcpyAsync(const_cast<float*>(a.obs), obs.data(), sizeof(float) * obs.size(),
+                       hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);  // obs is pageable host memory
+    if (e != hipSuccess) return e;
+  }
+  float x[12] = {0};
+  for (int c = 0; c < a.P.d; ++c) x[c] = x_init[c];
+  hipLaunchKernelGGL(k_init, dim3(1), dim3(NT), 0, stream, a.hdr, a.bar_flags, n_flags, a.states,
+                     a.actions, a.parents, a.costs, a.P.n_cap, a.P.d, a.P.m, x[0], x[1], x[2], x[3],
+                     x[4], x[5], x[6], x[7], x[8], x[9], x[10], x[11], a.P.c0);
+  return hipGetLastError();
+}
+
+struct DeviceInfo {
+  int device = 0, n_cu = 0, coop = 0, lds_cu = 0, lds_max = 0;
+  double ticks_per_ms = 100000.0;
+};
+
+hipError_t device_info(DeviceInfo* di) {
+  int wclk = 0;
+  hipError_t e = hipGetDevice(&di->device);
+  if (e == hipSuccess)
+    e = hipDeviceGetAttribute(&di->n_cu, hipDeviceAttributeMultiprocessorCount, di->device);
+  if (e == hipSuccess)
+    e = hipDeviceGetAttribute(&di->coop, hipDeviceAttributeCooperativeLaunch, di->device);
+  if (e == hipSuccess)
+    e = hipDeviceGetAttribute(&wclk, hipDeviceAttributeWallClockRate, di->device);
+  if (e == hipSuccess)
+    e = hipDeviceGetAttribute(&di->lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                              di->device);
+  if (e == hipSuccess)
+    e = hipDeviceGetAttribute(&di->lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, di->device);
+  if (wclk > 0) di->ticks_per_ms = (double)wclk;
+  return e;
+}
+
+void fill_stats(const DevHeader& h, double tpm, int grid, pakr_stats* out) {
+  std::memset(out, 0, sizeof *out);
+  out->n_nodes = h.n;
+  out->round = h.round;
+  out->iter = h.iter;
+  out->status = h.status;
+  out->n_solutions = h.n_solutions;
+  out->grid = grid;
+  out->total_iters = (long long)h.total_iters;
+  out->expansions = (long long)h.expansions;
+  out->insertions = (long long)h.insertions;
+  out->nn_pairs = (long long)h.nn_pairs;
+  out->c_best = std::isinf(h.c_best) ? INFINITY : (double)h.c_best;
+  out->call_ms = (double)(h.t_end - h.t_start) / tpm;
+  out->t_first_ms = h.t_first >= 0 ? (double)h.t_first / tpm : -1.0;
+  out->t_last_ms = h.t_last >= 0 ? (double)h.t_last / tpm : -1.0;
+  out->call_iters = h.call_iters;
+  out->call_rounds = h.call_rounds;
+  out->call_solutions = h.call_solutions;
+  for (int i = 0; i < 6; ++i) out->step_ms[i] = (double)h.ticks[i] / tpm;
+  out->nn_ms = out->step_ms[0] + out->step_ms[1];
+  out->rollout_ms = out->step_ms[2] + out->step_ms[3] + out->step_ms[4];
+  out->insert_ms = out->step_ms[5];
+  out->clock_start_ms = (double)h.t_start / tpm;
+  out->clock_end_ms = (double)h.t_end / tpm;
+}
+
+// Shared read-back helpers (each syncs `stream`).
+hipError_t read_header(const KArgs& a, hipStream_t stream, DevHeader* h) {
+  hipError_t e = hipMemcpyAsync(h, a.hdr, sizeof(DevHeader), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  return e;
+}
+
+hipError_t read_solutions(const KArgs& a, double tpm, int n, pakr_solution* out) {
+  if (n <= 0) return hipSuccess;
+  std::vector<DevSolution> tmp((size_t)n);
+  hipError_t e = hipMemcpy(tmp.data(), a.sols, sizeof(DevSolution) * n, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return e;
+  for (int i = 0; i < n; ++i) {
+    out[i].round = tmp[i].round;
+    out[i].iter = tmp[i].iter;
+    out[i].node = tmp[i].node;
+    out[i].n_nodes = tmp[i].n_nodes;
+    out[i].total_iter = tmp[i].total_iter;
+    out[i].cost = (double)tmp[i].cost;
+    out[i].t_ms = (double)tmp[i].t / tpm;
+  }
+  return hipSuccess;
+}
+
+// The stored best path is goal first; return it root first.
+hipError_t read_path(const KArgs& a, int ne, float* states, float* actions) {
+  const int d = a.P.d, m = a.P.m;
+  std::vector<float> rs((size_t)(ne + 1) * d), ra((size_t)ne * m + 1);
+  hipError_t e = hipMemcpy(rs.data(), a.path_states, sizeof(float) * rs.size(),
+                           hipMemcpyDeviceToHost);
+  if (e == hipSuccess && ne > 0)
+    e = hipMemcpy(ra.data(), a.path_actions, sizeof(float) * (size_t)ne * m,
+                  hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return e;
+  for (int k = 0; k <= ne; ++k)
+    std::memcpy(states + (size_t)k * d, rs.data() + (size_t)(ne - k) * d, sizeof(float) * d);
+  for (int k = 0; k < ne; ++k)
+    std::memcpy(actions + (size_t)k * m, ra.data() + (size_t)(ne - 1 - k) * m, sizeof(float) * m);
+  return hipSuccess;
+}
+
 }  // namespace
 
 struct pakr_plan {
-  pakr_system sys;
-  pakr_params prm;
-  DevProblem P;
+  KArgs args;          // buffers and problem record; limits set per call
   int G = 0, qt = 1;
-  int device = 0;
   hipStream_t stream = nullptr;
   double ticks_per_ms = 100000.0;
   void* ws = nullptr;
   bool own_ws = false;
-  size_t ws_bytes = 0;
   Layout L{};
   const void* kfn = nullptr;
   size_t shmem = 0;
   bool broken = false;
   std::string err;
-  template <typename T>
-  T* at(size_t off) const {
-    return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
-  }
+};
+
+struct pakr_batch {
+  int nq = 0, G = 0;
+  hipStream_t stream = nullptr;
+  double ticks_per_ms = 100000.0;
+  void* ws = nullptr;
+  bool own_ws = false;
+  std::vector<KArgs> args;
+  KArgs* d_args = nullptr;
+  int* d_queue = nullptr;
+  size_t shmem = 0;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  bool broken = false;
+  std::string err;
 };
 
 namespace {
@@ -251,11 +476,18 @@ int fail(pakr_plan* pl, int code, const std::string& msg) {
 }
 
 int hip_fail(pakr_plan* pl, hipError_t e, const char* what) {
-  std::string m = std::string(what) + ": " + hipGetErrorString(e);
-  return fail(pl, PAKR_E_HIP, m);
+  return fail(pl, PAKR_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-int qt_for(int K) { return K <= NT ? 1 : (K <= 2 * NT ? 2 : 4); }
+int bfail(pakr_batch* bt, int code, const std::string& msg) {
+  if (bt) bt->err = msg;
+  else g_init_error = msg;
+  return code;
+}
+
+int bhip_fail(pakr_batch* bt, hipError_t e, const char* what) {
+  return bfail(bt, PAKR_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
 
 }  // namespace
 
@@ -271,12 +503,9 @@ size_t pakr_workspace_size(const pakr_system* sys, const pakr_params* params,
   const int G = params->grid > 0 ? params->grid : AUTO_GRID_MAX;
   const int nb = std::max(scene->n_box, 0), ns = std::max(scene->n_sphere, 0);
   const int of = obs_floats_of(sys_npos(sys->id), nb, ns);
-  size_t worst = 0;  // the auto lane choice may differ; size for the largest layout
-  for (int lanes = 1; lanes <= 8; lanes <<= 1) {
-    pakr_params q = *params;
-    q.lanes_per_candidate = lanes;
-    worst = std::max(worst, make_layout(d, m, q, G, of, lanes).total);
-  }
+  size_t worst = 0;  // the lane choice depends on the device; size for the largest layout
+  for (int lanes = 1; lanes <= 8; lanes <<= 1)
+    worst = std::max(worst, make_layout(d, m, *params, G, of, lanes).total);
   return worst;
 }
 
@@ -289,35 +518,19 @@ int pakr_plan_init(const pakr_system* sys, const pakr_scene* scene, const float*
   const std::string msg = validate(sys, scene, x_init, goal, params, &code);
   if (code != PAKR_OK) return fail(nullptr, code, msg);
 
+  DeviceInfo di;
+  hipError_t e = device_info(&di);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "device query");
+  if (!di.coop) return fail(nullptr, PAKR_E_HIP, "device does not support cooperative launches");
+
   pakr_plan* pl = new (std::nothrow) pakr_plan();
   if (!pl) return fail(nullptr, PAKR_E_INVALID_ARG, "out of host memory");
-  pl->sys = *sys;
-  pl->prm = *params;
   pl->stream = static_cast<hipStream_t>(stream);
-  hipError_t e = hipGetDevice(&pl->device);
-  if (e != hipSuccess) {
-    int rc = hip_fail(nullptr, e, "hipGetDevice");
-    delete pl;
-    return rc;
-  }
-  int n_cu = 0, coop = 0, wclk_khz = 0;
-  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, pl->device) != hipSuccess ||
-      hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, pl->device) != hipSuccess ||
-      hipDeviceGetAttribute(&wclk_khz, hipDeviceAttributeWallClockRate, pl->device) != hipSuccess) {
-    delete pl;
-    return fail(nullptr, PAKR_E_HIP, "device attribute query failed");
-  }
-  if (wclk_khz > 0) pl->ticks_per_ms = (double)wclk_khz;
-  if (!coop) {
-    delete pl;
-    return fail(nullptr, PAKR_E_HIP, "device does not support cooperative launches");
-  }
-
-  const int d = sys->d, m = sys->m, P = scene->npos;
+  pl->ticks_per_ms = di.ticks_per_ms;
   const int K = params->B / params->A;
   pl->qt = qt_for(K);
   pl->kfn = kernel_for(sys->id, pl->qt);
-  const int of = obs_floats_of(P, scene->n_box, scene->n_sphere);
+  const int of = obs_floats_of(scene->npos, scene->n_box, scene->n_sphere);
   const size_t obs_bytes = sizeof(float) * (size_t)std::max(of, 1);
   pl->shmem = obs_bytes;
   int G = 0;
@@ -327,20 +540,15 @@ int pakr_plan_init(const pakr_system* sys, const pakr_scene* scene, const float*
     // k workgroups on every CU: reserve enough LDS that a CU cannot hold k+1,
     // so the co-resident grid of k * CUs is spread evenly
     const int k = params->workgroups_per_cu > 0 ? params->workgroups_per_cu : 1;
-    int lds_cu = 0, lds_max = 0;
     hipFuncAttributes fa;
-    if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
-                              pl->device) != hipSuccess ||
-        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, pl->device) !=
-            hipSuccess ||
-        hipFuncGetAttributes(&fa, pl->kfn) != hipSuccess) {
+    if (hipFuncGetAttributes(&fa, pl->kfn) != hipSuccess) {
       delete pl;
-      return fail(nullptr, PAKR_E_HIP, "LDS attribute query failed");
+      return fail(nullptr, PAKR_E_HIP, "kernel attribute query failed");
     }
-    const size_t want = (size_t)lds_cu / (size_t)(k + 1) + 1024;  // > LDS/(k+1) per workgroup
+    const size_t want = (size_t)di.lds_cu / (size_t)(k + 1) + 1024;  // > LDS/(k+1)
     const size_t dyn = want > fa.sharedSizeBytes ? want - fa.sharedSizeBytes : 0;
-    if (dyn + fa.sharedSizeBytes <= (size_t)lds_max && dyn > obs_bytes) pl->shmem = dyn;
-    G = k * n_cu;
+    if (dyn + fa.sharedSizeBytes <= (size_t)di.lds_max && dyn > obs_bytes) pl->shmem = dyn;
+    G = k * di.n_cu;
   }
   int per_cu = 0;
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pl->kfn, NT, pl->shmem);
@@ -350,23 +558,22 @@ int pakr_plan_init(const pakr_system* sys, const pakr_scene* scene, const float*
     delete pl;
     return rc;
   }
-  const int max_coresident = per_cu * n_cu;
-  if (params->grid <= 0) G = std::min(G, max_coresident);
+  const int max_coresident = per_cu * di.n_cu;
+  if (params->grid <= 0) G = std::min(std::min(G, max_coresident), AUTO_GRID_MAX);
   const int lanes = lanes_for(*params, scene->n_box + scene->n_sphere,
                               params->grid > 0 ? G : max_coresident);
   const int cpb = NT / lanes;
   const int GR = (params->B + cpb - 1) / cpb;
   if (G < GR) G = params->grid > 0 ? -1 : GR;
-  if (G < 1 || G > max_coresident) {
+  if (G < 1 || G > max_coresident || G > AUTO_GRID_MAX) {
     char buf[160];
     snprintf(buf, sizeof buf, "grid %d invalid: need >= %d rollout workgroups and <= %d co-resident",
-             params->grid > 0 ? params->grid : G, GR, max_coresident);
+             params->grid > 0 ? params->grid : G, GR, std::min(max_coresident, AUTO_GRID_MAX));
     delete pl;
     return fail(nullptr, PAKR_E_INVALID_ARG, buf);
   }
   pl->G = G;
-
-  pl->L = make_layout(d, m, *params, G, of, lanes);
+  pl->L = make_layout(sys->d, sys->m, *params, G, of, lanes);
   const size_t need = pl->L.total;
   if (d_workspace) {
     if (ws_bytes < need) {
@@ -378,7 +585,6 @@ int pakr_plan_init(const pakr_system* sys, const pakr_scene* scene, const float*
       return fail(nullptr, PAKR_E_INVALID_ARG, "workspace must be 256-byte aligned");
     }
     pl->ws = d_workspace;
-    pl->ws_bytes = ws_bytes;
   } else {
     e = hipMalloc(&pl->ws, need);
     if (e != hipSuccess) {
@@ -387,97 +593,12 @@ int pakr_plan_init(const pakr_system* sys, const pakr_scene* scene, const float*
       return rc;
     }
     pl->own_ws = true;
-    pl->ws_bytes = need;
   }
-
-  DevProblem& Q = pl->P;
-  std::memset(&Q, 0, sizeof Q);
-  Q.system = sys->id;
-  Q.d = d;
-  Q.m = m;
-  Q.npos = P;
-  Q.B = params->B;
-  Q.A = params->A;
-  Q.K = K;
-  Q.T = params->T;
-  Q.n_cap = params->n_cap;
-  Q.cost_kind = params->cost_kind;
-  Q.h_kind = params->heuristic_kind;
-  Q.max_iters_per_round = params->max_iters_per_round;
-  Q.n_box = scene->n_box;
-  Q.n_sph = scene->n_sphere;
-  Q.G = G;
-  Q.G_roll = GR;
-  Q.lanes = lanes;
-  Q.cpb = cpb;
-  Q.max_path_edges = params->max_path_edges > 0 ? params->max_path_edges : DEFAULT_PATH_EDGES;
-  Q.obs_floats = of;
-  Q.key0 = (uint32_t)(params->seed & 0xffffffffull);
-  Q.key1 = params->query_id;
-  Q.dt = params->dt;
-  Q.h_speed = params->h_speed;
-  Q.c0 = (float)params->cost_bound;
-  Q.vnorm_max = sys->vnorm_max;
-  Q.goal_r = goal->radius;
-  Q.goal_r2 = goal->radius * goal->radius;
-  {
-    volatile float tf = (float)params->T;
-    volatile float ed = tf * params->dt;  // one float32 rounding
-    Q.edge_duration = ed;
-  }
-  for (int i = 0; i < 8; ++i) Q.dyn[i] = sys->dyn[i];
-  for (int i = 0; i < PAKR_MAX_D; ++i) {
-    Q.sample_lo[i] = sys->sample_lo[i];
-    Q.sample_hi[i] = sys->sample_hi[i];
-    Q.lim_lo[i] = sys->lim_lo[i];
-    Q.lim_hi[i] = sys->lim_hi[i];
-  }
-  for (int i = 0; i < PAKR_MAX_M; ++i) {
-    Q.u_lo[i] = sys->u_lo[i];
-    Q.u_hi[i] = sys->u_hi[i];
-  }
-  for (int c = 0; c < 3; ++c) {
-    Q.ws_lo[c] = c < P ? scene->ws_lo[c] : 0.0f;
-    Q.ws_hi[c] = c < P ? scene->ws_hi[c] : 0.0f;
-    Q.goal_c[c] = c < P ? goal->center[c] : 0.0f;
-  }
-
-  // pack obstacles: boxes (c[P], h[P]) then spheres (c[P], r^2)
-  float* obs_h = static_cast<float*>(std::malloc(sizeof(float) * (size_t)std::max(of, 1)));
-  if (!obs_h) {
-    pakr_plan_destroy(pl);
-    return fail(nullptr, PAKR_E_INVALID_ARG, "out of host memory");
-  }
-  int w = 0;
-  for (int b = 0; b < scene->n_box; ++b) {
-    for (int c = 0; c < P; ++c) obs_h[w++] = scene->box_c[b * P + c];
-    for (int c = 0; c < P; ++c) obs_h[w++] = scene->box_h[b * P + c];
-  }
-  for (int q = 0; q < scene->n_sphere; ++q) {
-    for (int c = 0; c < P; ++c) obs_h[w++] = scene->sph_c[q * P + c];
-    obs_h[w++] = scene->sph_r[q] * scene->sph_r[q];
-  }
-  if (of > 0) {
-    e = hipMemcpyAsync(pl->at<float>(pl->L.obs), obs_h, sizeof(float) * of,
-                       hipMemcpyHostToDevice, pl->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(pl->stream);  // obs_h is pageable, freed below
-  }
-  std::free(obs_h);
+  const DevProblem Q = make_problem(*sys, *scene, *goal, *params, G, lanes);
+  pl->args = make_args(Q, static_cast<char*>(pl->ws), pl->L);
+  e = upload_query(pl->args, pack_obstacles(*scene), x_init, G, pl->stream);
   if (e != hipSuccess) {
-    int rc = hip_fail(nullptr, e, "copy obstacles");
-    pakr_plan_destroy(pl);
-    return rc;
-  }
-  float x[12] = {0};
-  for (int c = 0; c < d; ++c) x[c] = x_init[c];
-  hipLaunchKernelGGL(k_init, dim3(1), dim3(NT), 0, pl->stream, pl->at<DevHeader>(pl->L.hdr),
-                     pl->at<uint32_t>(pl->L.bar), G, pl->at<float>(pl->L.states),
-                     pl->at<float>(pl->L.actions), pl->at<int>(pl->L.parents),
-                     pl->at<float>(pl->L.costs), params->n_cap, d, m, x[0], x[1], x[2], x[3], x[4],
-                     x[5], x[6], x[7], x[8], x[9], x[10], x[11], Q.c0);
-  e = hipGetLastError();
-  if (e != hipSuccess) {
-    int rc = hip_fail(nullptr, e, "launch k_init");
+    int rc = hip_fail(nullptr, e, "upload query");
     pakr_plan_destroy(pl);
     return rc;
   }
@@ -494,7 +615,7 @@ void pakr_plan_destroy(pakr_plan* pl) {
 
 size_t pakr_trace_bytes(const pakr_plan* pl, int n_iters) {
   if (!pl || n_iters < 0) return 0;
-  const size_t K = pl->P.K, B = pl->P.B, d = pl->P.d, m = pl->P.m;
+  const size_t K = pl->args.P.K, B = pl->args.P.B, d = pl->args.P.d, m = pl->args.P.m;
   const size_t words = TRACE_HDR_WORDS + K * d + K + B * m + B * d + 3 * B;
   return words * 4 * (size_t)n_iters;
 }
@@ -504,32 +625,11 @@ namespace {
 int launch(pakr_plan* pl, long long max_iters, long long max_rounds, double budget_ms,
            int* trace, long long trace_iters) {
   if (pl->broken) return fail(pl, PAKR_E_DEVICE, "plan is unusable after a device error");
-  KArgs a;
-  std::memset(&a, 0, sizeof a);
-  a.P = pl->P;
-  a.hdr = pl->at<DevHeader>(pl->L.hdr);
-  a.bar_flags = pl->at<uint32_t>(pl->L.bar);
-  a.sols = pl->at<DevSolution>(pl->L.sols);
-  a.path_states = pl->at<float>(pl->L.pstates);
-  a.path_actions = pl->at<float>(pl->L.pactions);
-  a.states = pl->at<float>(pl->L.states);
-  a.actions = pl->at<float>(pl->L.actions);
-  a.parents = pl->at<int>(pl->L.parents);
-  a.costs = pl->at<float>(pl->L.costs);
-  a.obs = pl->at<float>(pl->L.obs);
-  a.partial = pl->at<unsigned long long>(pl->L.partial);
-  a.stg = pl->at<float>(pl->L.stg);
-  a.counts = pl->at<int>(pl->L.counts);
-  a.goalmin = pl->at<unsigned long long>(pl->L.goalmin);
+  KArgs a = pl->args;
+  set_limits(a, max_iters, max_rounds, budget_ms, pl->ticks_per_ms);
   a.trace = trace;
   a.trace_words = (long long)(pakr_trace_bytes(pl, 1) / 4);
   a.trace_iters = trace ? trace_iters : 0;
-  a.max_iters = max_iters;
-  a.max_rounds = max_rounds;
-  a.budget_ticks = budget_ms > 0 ? (long long)(budget_ms * pl->ticks_per_ms) : 0;
-  const double guard_ms = (budget_ms > 0 ? budget_ms : 0.0) + 60000.0;
-  a.guard_ticks = (long long)(guard_ms * pl->ticks_per_ms);
-  a.barrier_timeout_ticks = (long long)(2000.0 * pl->ticks_per_ms);
   void* args[] = {&a};
   hipError_t e = hipLaunchCooperativeKernel(pl->kfn, dim3(pl->G), dim3(NT), args,
                                             (unsigned)pl->shmem, pl->stream);
@@ -538,9 +638,7 @@ int launch(pakr_plan* pl, long long max_iters, long long max_rounds, double budg
 }
 
 int sync_header(pakr_plan* pl, DevHeader* h) {
-  hipError_t e = hipMemcpyAsync(h, pl->at<DevHeader>(pl->L.hdr), sizeof(DevHeader),
-                                hipMemcpyDeviceToHost, pl->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(pl->stream);
+  hipError_t e = read_header(pl->args, pl->stream, h);
   if (e != hipSuccess) return hip_fail(pl, e, "read header");
   if (h->err != 0) {
     pl->broken = true;
@@ -562,9 +660,9 @@ int pakr_expand(pakr_plan* pl, int n_iters, void* d_trace, size_t trace_bytes) {
 
 int pakr_replan(pakr_plan* pl, double budget_ms, int max_rounds, long long max_iters) {
   if (!pl) return PAKR_E_INVALID_ARG;
+  if (std::isnan(budget_ms)) return fail(pl, PAKR_E_INVALID_ARG, "budget is NaN");
   if (!(budget_ms > 0) && max_rounds <= 0 && max_iters <= 0)
     return fail(pl, PAKR_E_INVALID_ARG, "set a budget, a round limit or an iteration limit");
-  if (std::isnan(budget_ms)) return fail(pl, PAKR_E_INVALID_ARG, "budget is NaN");
   return launch(pl, max_iters, max_rounds, budget_ms, nullptr, 0);
 }
 
@@ -573,28 +671,7 @@ int pakr_status(pakr_plan* pl, pakr_stats* out) {
   DevHeader h;
   int rc = sync_header(pl, &h);
   if (rc != PAKR_OK) return rc;
-  std::memset(out, 0, sizeof *out);
-  out->n_nodes = h.n;
-  out->round = h.round;
-  out->iter = h.iter;
-  out->status = h.status;
-  out->n_solutions = h.n_solutions;
-  out->grid = pl->G;
-  out->total_iters = (long long)h.total_iters;
-  out->expansions = (long long)h.expansions;
-  out->insertions = (long long)h.insertions;
-  out->nn_pairs = (long long)h.nn_pairs;
-  out->c_best = std::isinf(h.c_best) ? INFINITY : (double)h.c_best;
-  out->call_ms = (double)(h.t_end - h.t_start) / pl->ticks_per_ms;
-  out->t_first_ms = h.t_first >= 0 ? (double)h.t_first / pl->ticks_per_ms : -1.0;
-  out->t_last_ms = h.t_last >= 0 ? (double)h.t_last / pl->ticks_per_ms : -1.0;
-  out->call_iters = h.call_iters;
-  out->call_rounds = h.call_rounds;
-  out->call_solutions = h.call_solutions;
-  for (int i = 0; i < 6; ++i) out->step_ms[i] = (double)h.ticks[i] / pl->ticks_per_ms;
-  out->nn_ms = out->step_ms[0] + out->step_ms[1];
-  out->rollout_ms = out->step_ms[2] + out->step_ms[3] + out->step_ms[4];
-  out->insert_ms = out->step_ms[5];
+  fill_stats(h, pl->ticks_per_ms, pl->G, out);
   return PAKR_OK;
 }
 
@@ -605,25 +682,8 @@ int pakr_solutions(pakr_plan* pl, pakr_solution* out, int cap, int* n_total) {
   if (rc != PAKR_OK) return rc;
   *n_total = h.n_solutions;
   const int n = std::min(std::min(cap, h.n_solutions), MAX_SOLUTIONS);
-  if (n <= 0) return PAKR_OK;
-  DevSolution* tmp = new (std::nothrow) DevSolution[n];
-  if (!tmp) return fail(pl, PAKR_E_INVALID_ARG, "out of host memory");
-  hipError_t e = hipMemcpy(tmp, pl->at<DevSolution>(pl->L.sols), sizeof(DevSolution) * n,
-                           hipMemcpyDeviceToHost);
-  if (e != hipSuccess) {
-    delete[] tmp;
-    return hip_fail(pl, e, "read solutions");
-  }
-  for (int i = 0; i < n; ++i) {
-    out[i].round = tmp[i].round;
-    out[i].iter = tmp[i].iter;
-    out[i].node = tmp[i].node;
-    out[i].n_nodes = tmp[i].n_nodes;
-    out[i].total_iter = tmp[i].total_iter;
-    out[i].cost = (double)tmp[i].cost;
-    out[i].t_ms = (double)tmp[i].t / pl->ticks_per_ms;
-  }
-  delete[] tmp;
+  hipError_t e = read_solutions(pl->args, pl->ticks_per_ms, n, out);
+  if (e != hipSuccess) return hip_fail(pl, e, "read solutions");
   return PAKR_OK;
 }
 
@@ -637,36 +697,13 @@ int pakr_extract_path(pakr_plan* pl, float* states, float* actions, int cap_edge
     *n_edges = 0;
     return fail(pl, PAKR_E_NO_SOLUTION, "no solution yet");
   }
-  const int ne = h.best_edges, d = pl->P.d, m = pl->P.m;
-  *n_edges = ne;
+  *n_edges = h.best_edges;
   if (cost) *cost = (double)h.best_cost;
   if (h.path_truncated) return fail(pl, PAKR_E_BUFFER_TOO_SMALL, "path longer than max_path_edges");
-  if (ne > cap_edges) return fail(pl, PAKR_E_BUFFER_TOO_SMALL, "cap_edges too small");
+  if (h.best_edges > cap_edges) return fail(pl, PAKR_E_BUFFER_TOO_SMALL, "cap_edges too small");
   if (!states || !actions) return fail(pl, PAKR_E_INVALID_ARG, "null output arrays");
-  float* rs = new (std::nothrow) float[(size_t)(ne + 1) * d];
-  float* ra = new (std::nothrow) float[(size_t)ne * m + 1];
-  if (!rs || !ra) {
-    delete[] rs;
-    delete[] ra;
-    return fail(pl, PAKR_E_INVALID_ARG, "out of host memory");
-  }
-  hipError_t e = hipMemcpy(rs, pl->at<float>(pl->L.pstates), sizeof(float) * (size_t)(ne + 1) * d,
-                           hipMemcpyDeviceToHost);
-  if (e == hipSuccess)
-    e = hipMemcpy(ra, pl->at<float>(pl->L.pactions), sizeof(float) * (size_t)ne * m,
-                  hipMemcpyDeviceToHost);
-  if (e != hipSuccess) {
-    delete[] rs;
-    delete[] ra;
-    return hip_fail(pl, e, "read path");
-  }
-  // stored goal first; return root first
-  for (int k = 0; k <= ne; ++k)
-    std::memcpy(states + (size_t)k * d, rs + (size_t)(ne - k) * d, sizeof(float) * d);
-  for (int k = 0; k < ne; ++k)
-    std::memcpy(actions + (size_t)k * m, ra + (size_t)(ne - 1 - k) * m, sizeof(float) * m);
-  delete[] rs;
-  delete[] ra;
+  hipError_t e = read_path(pl->args, h.best_edges, states, actions);
+  if (e != hipSuccess) return hip_fail(pl, e, "read path");
   return PAKR_OK;
 }
 
@@ -678,28 +715,26 @@ int pakr_copy_tree(pakr_plan* pl, float* states, float* actions, int* parents, f
   if (rc != PAKR_OK) return rc;
   *n_out = h.n;
   const int n = std::min(h.n, n_max);
-  const int d = pl->P.d, m = pl->P.m;
-  const size_t N = (size_t)pl->P.n_cap;
+  const int d = pl->args.P.d, m = pl->args.P.m;
+  const size_t N = (size_t)pl->args.P.n_cap;
   hipError_t e = hipSuccess;
   if (n > 0 && (states || actions)) {
-    float* tmp = new (std::nothrow) float[(size_t)n];
-    if (!tmp) return fail(pl, PAKR_E_INVALID_ARG, "out of host memory");
+    std::vector<float> tmp((size_t)n);
     for (int c = 0; c < d && states && e == hipSuccess; ++c) {
-      e = hipMemcpy(tmp, pl->at<float>(pl->L.states) + (size_t)c * N, sizeof(float) * n,
+      e = hipMemcpy(tmp.data(), pl->args.states + (size_t)c * N, sizeof(float) * n,
                     hipMemcpyDeviceToHost);
       for (int i = 0; i < n; ++i) states[(size_t)i * d + c] = tmp[i];
     }
     for (int c = 0; c < m && actions && e == hipSuccess; ++c) {
-      e = hipMemcpy(tmp, pl->at<float>(pl->L.actions) + (size_t)c * N, sizeof(float) * n,
+      e = hipMemcpy(tmp.data(), pl->args.actions + (size_t)c * N, sizeof(float) * n,
                     hipMemcpyDeviceToHost);
       for (int i = 0; i < n; ++i) actions[(size_t)i * m + c] = tmp[i];
     }
-    delete[] tmp;
   }
   if (e == hipSuccess && n > 0 && parents)
-    e = hipMemcpy(parents, pl->at<int>(pl->L.parents), sizeof(int) * n, hipMemcpyDeviceToHost);
+    e = hipMemcpy(parents, pl->args.parents, sizeof(int) * n, hipMemcpyDeviceToHost);
   if (e == hipSuccess && n > 0 && costs)
-    e = hipMemcpy(costs, pl->at<float>(pl->L.costs), sizeof(float) * n, hipMemcpyDeviceToHost);
+    e = hipMemcpy(costs, pl->args.costs, sizeof(float) * n, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(pl, e, "read tree");
   return PAKR_OK;
 }
@@ -721,6 +756,258 @@ const char* pakr_error_string(int code) {
     case PAKR_E_DEVICE: return "PAKR_E_DEVICE";
   }
   return "unknown";
+}
+
+// ---------------------------------------------------------------------------
+// Batched planning
+// ---------------------------------------------------------------------------
+
+namespace {
+
+int batch_lanes(const pakr_params& p) { return p.lanes_per_candidate > 0 ? p.lanes_per_candidate : 1; }
+
+// Offsets of the batch workspace: queue word, argument table, then one
+// single-workgroup query layout after another.
+size_t batch_layout(int n, const pakr_system* sys, const pakr_scene* sc, const pakr_params* prm,
+                    std::vector<size_t>* bases, std::vector<Layout>* layouts) {
+  size_t off = 256 + align_up(sizeof(KArgs) * (size_t)n);
+  for (int q = 0; q < n; ++q) {
+    const int of = obs_floats_of(sc[q].npos, sc[q].n_box, sc[q].n_sphere);
+    const Layout L = make_layout(sys[q].d, sys[q].m, prm[q], 1, of, batch_lanes(prm[q]));
+    if (bases) bases->push_back(off);
+    if (layouts) layouts->push_back(L);
+    off = align_up(off + L.total);
+  }
+  return off;
+}
+
+}  // namespace
+
+size_t pakr_batch_workspace_size(int n, const pakr_system* sys, const pakr_scene* scenes,
+                                 const pakr_params* params) {
+  if (n < 1 || !sys || !scenes || !params) return 0;
+  for (int q = 0; q < n; ++q) {
+    if (sys_d(sys[q].id) < 0 || sys[q].d != sys_d(sys[q].id) || sys[q].m != sys_m(sys[q].id) ||
+        params[q].A < 1 || params[q].B < 1 || params[q].B % params[q].A != 0 ||
+        params[q].n_cap < 1 || scenes[q].n_box < 0 || scenes[q].n_sphere < 0)
+      return 0;
+  }
+  return batch_layout(n, sys, scenes, params, nullptr, nullptr);
+}
+
+int pakr_batch_init(int n, const pakr_system* sys, const pakr_scene* scenes,
+                    const float* const* x_inits, const pakr_goal* goals,
+                    const pakr_params* params, void* d_workspace, size_t ws_bytes, void* stream,
+                    pakr_batch** out) {
+  if (!out) return bfail(nullptr, PAKR_E_INVALID_ARG, "out is null");
+  *out = nullptr;
+  if (n < 1 || !sys || !scenes || !x_inits || !goals || !params)
+    return bfail(nullptr, PAKR_E_INVALID_ARG, "null argument or n < 1");
+  int max_obs = 1;
+  for (int q = 0; q < n; ++q) {
+    int code = PAKR_OK;
+    const std::string msg = validate(&sys[q], &scenes[q], x_inits[q], &goals[q], &params[q], &code);
+    if (code != PAKR_OK) return bfail(nullptr, code, "query " + std::to_string(q) + ": " + msg);
+    const int L = batch_lanes(params[q]);
+    if ((params[q].B + NT / L - 1) / (NT / L) > MAX_GR)
+      return bfail(nullptr, PAKR_E_INVALID_ARG,
+                   "query " + std::to_string(q) + ": too many rollout chunks for the lane count");
+    max_obs = std::max(max_obs, obs_floats_of(scenes[q].npos, scenes[q].n_box, scenes[q].n_sphere));
+  }
+  DeviceInfo di;
+  hipError_t e = device_info(&di);
+  if (e != hipSuccess) return bhip_fail(nullptr, e, "device query");
+
+  pakr_batch* bt = new (std::nothrow) pakr_batch();
+  if (!bt) return bfail(nullptr, PAKR_E_INVALID_ARG, "out of host memory");
+  bt->nq = n;
+  bt->stream = static_cast<hipStream_t>(stream);
+  bt->ticks_per_ms = di.ticks_per_ms;
+  bt->shmem = sizeof(float) * (size_t)max_obs;
+  int per_cu = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_batch),
+                                                   NT, bt->shmem);
+  if (e != hipSuccess || per_cu < 1) {
+    int rc = e != hipSuccess ? bhip_fail(nullptr, e, "occupancy query")
+                             : bfail(nullptr, PAKR_E_HIP, "batch kernel does not fit on a CU");
+    delete bt;
+    return rc;
+  }
+  bt->G = std::max(1, std::min(n, per_cu * di.n_cu));
+
+  std::vector<size_t> bases;
+  std::vector<Layout> layouts;
+  const size_t need = batch_layout(n, sys, scenes, params, &bases, &layouts);
+  if (d_workspace) {
+    if (ws_bytes < need || (reinterpret_cast<uintptr_t>(d_workspace) & 255) != 0) {
+      delete bt;
+      return bfail(nullptr, ws_bytes < need ? PAKR_E_WORKSPACE_TOO_SMALL : PAKR_E_INVALID_ARG,
+                   ws_bytes < need ? "workspace smaller than required"
+                                   : "workspace must be 256-byte aligned");
+    }
+    bt->ws = d_workspace;
+  } else {
+    e = hipMalloc(&bt->ws, need);
+    if (e != hipSuccess) {
+      int rc = bhip_fail(nullptr, e, "hipMalloc workspace");
+      delete bt;
+      return rc;
+    }
+    bt->own_ws = true;
+  }
+  char* base = static_cast<char*>(bt->ws);
+  bt->d_queue = reinterpret_cast<int*>(base);
+  bt->d_args = reinterpret_cast<KArgs*>(base + 256);
+  bt->args.resize((size_t)n);
+  for (int q = 0; q < n; ++q) {
+    const DevProblem Q = make_problem(sys[q], scenes[q], goals[q], params[q], 1, batch_lanes(params[q]));
+    bt->args[q] = make_args(Q, base + bases[q], layouts[q]);
+    e = upload_query(bt->args[q], pack_obstacles(scenes[q]), x_inits[q], 1, bt->stream);
+    if (e != hipSuccess) {
+      int rc = bhip_fail(nullptr, e, "upload query");
+      pakr_batch_destroy(bt);
+      return rc;
+    }
+  }
+  *out = bt;
+  return PAKR_OK;
+}
+
+namespace {
+
+// Upload the argument table with these limits and enqueue reset + launch on `s`.
+int batch_enqueue(pakr_batch* bt, double budget_ms, int max_rounds, long long max_iters,
+                  hipStream_t s, bool upload) {
+  if (upload) {
+    for (auto& a : bt->args) set_limits(a, max_iters, max_rounds, budget_ms, bt->ticks_per_ms);
+    hipError_t e = hipMemcpyAsync(bt->d_args, bt->args.data(), sizeof(KArgs) * bt->args.size(),
+                                  hipMemcpyHostToDevice, bt->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(bt->stream);  // pageable source
+    if (e != hipSuccess) return bhip_fail(bt, e, "upload batch arguments");
+  }
+  hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, bt->d_queue);
+  hipLaunchKernelGGL(k_batch, dim3(bt->G), dim3(NT), bt->shmem, s,
+                     static_cast<const KArgs*>(bt->d_args), bt->nq, bt->d_queue);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return bhip_fail(bt, e, "batch launch");
+  return PAKR_OK;
+}
+
+int batch_limits_ok(pakr_batch* bt, double budget_ms, int max_rounds, long long max_iters) {
+  if (std::isnan(budget_ms)) return bfail(bt, PAKR_E_INVALID_ARG, "budget is NaN");
+  if (!(budget_ms > 0) && max_rounds <= 0 && max_iters <= 0)
+    return bfail(bt, PAKR_E_INVALID_ARG, "set a budget, a round limit or an iteration limit");
+  return PAKR_OK;
+}
+
+}  // namespace
+
+int pakr_batch_replan(pakr_batch* bt, double budget_ms, int max_rounds, long long max_iters) {
+  if (!bt) return PAKR_E_INVALID_ARG;
+  int rc = batch_limits_ok(bt, budget_ms, max_rounds, max_iters);
+  if (rc != PAKR_OK) return rc;
+  return batch_enqueue(bt, budget_ms, max_rounds, max_iters, bt->stream, true);
+}
+
+int pakr_batch_graph_capture(pakr_batch* bt, double budget_ms, int max_rounds,
+                             long long max_iters) {
+  if (!bt) return PAKR_E_INVALID_ARG;
+  int rc = batch_limits_ok(bt, budget_ms, max_rounds, max_iters);
+  if (rc != PAKR_OK) return rc;
+  if (bt->gexec) {
+    (void)hipGraphExecDestroy(bt->gexec);
+    bt->gexec = nullptr;
+  }
+  if (bt->graph) {
+    (void)hipGraphDestroy(bt->graph);
+    bt->graph = nullptr;
+  }
+  hipError_t e = hipSuccess;
+  if (!bt->cap_stream) e = hipStreamCreateWithFlags(&bt->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) return bhip_fail(bt, e, "create capture stream");
+  // the argument table is uploaded once, outside the graph
+  for (auto& a : bt->args) set_limits(a, max_iters, max_rounds, budget_ms, bt->ticks_per_ms);
+  e = hipMemcpyAsync(bt->d_args, bt->args.data(), sizeof(KArgs) * bt->args.size(),
+                     hipMemcpyHostToDevice, bt->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(bt->stream);
+  if (e != hipSuccess) return bhip_fail(bt, e, "upload batch arguments");
+  e = hipStreamBeginCapture(bt->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return bhip_fail(bt, e, "begin capture");
+  rc = batch_enqueue(bt, budget_ms, max_rounds, max_iters, bt->cap_stream, false);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(bt->cap_stream, &g);
+  if (rc != PAKR_OK) return rc;
+  if (e != hipSuccess) return bhip_fail(bt, e, "end capture");
+  bt->graph = g;
+  e = hipGraphInstantiate(&bt->gexec, bt->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return bhip_fail(bt, e, "instantiate graph");
+  return PAKR_OK;
+}
+
+int pakr_batch_graph_launch(pakr_batch* bt) {
+  if (!bt) return PAKR_E_INVALID_ARG;
+  if (!bt->gexec) return bfail(bt, PAKR_E_INVALID_ARG, "no captured graph");
+  hipError_t e = hipGraphLaunch(bt->gexec, bt->stream);
+  if (e != hipSuccess) return bhip_fail(bt, e, "graph launch");
+  return PAKR_OK;
+}
+
+int pakr_batch_status(pakr_batch* bt, int q, pakr_stats* out) {
+  if (!bt || !out || q < 0 || q >= bt->nq) return PAKR_E_INVALID_ARG;
+  DevHeader h;
+  hipError_t e = read_header(bt->args[q], bt->stream, &h);
+  if (e != hipSuccess) return bhip_fail(bt, e, "read header");
+  fill_stats(h, bt->ticks_per_ms, bt->G, out);
+  return PAKR_OK;
+}
+
+int pakr_batch_solutions(pakr_batch* bt, int q, pakr_solution* out, int cap, int* n_total) {
+  if (!bt || !n_total || q < 0 || q >= bt->nq || cap < 0 || (cap > 0 && !out))
+    return PAKR_E_INVALID_ARG;
+  DevHeader h;
+  hipError_t e = read_header(bt->args[q], bt->stream, &h);
+  if (e != hipSuccess) return bhip_fail(bt, e, "read header");
+  *n_total = h.n_solutions;
+  e = read_solutions(bt->args[q], bt->ticks_per_ms,
+                     std::min(std::min(cap, h.n_solutions), MAX_SOLUTIONS), out);
+  if (e != hipSuccess) return bhip_fail(bt, e, "read solutions");
+  return PAKR_OK;
+}
+
+int pakr_batch_extract_path(pakr_batch* bt, int q, float* states, float* actions, int cap_edges,
+                            int* n_edges, double* cost) {
+  if (!bt || !n_edges || q < 0 || q >= bt->nq) return PAKR_E_INVALID_ARG;
+  DevHeader h;
+  hipError_t e = read_header(bt->args[q], bt->stream, &h);
+  if (e != hipSuccess) return bhip_fail(bt, e, "read header");
+  if (h.best_edges < 0) {
+    *n_edges = 0;
+    return bfail(bt, PAKR_E_NO_SOLUTION, "no solution yet");
+  }
+  *n_edges = h.best_edges;
+  if (cost) *cost = (double)h.best_cost;
+  if (h.path_truncated) return bfail(bt, PAKR_E_BUFFER_TOO_SMALL, "path longer than max_path_edges");
+  if (h.best_edges > cap_edges) return bfail(bt, PAKR_E_BUFFER_TOO_SMALL, "cap_edges too small");
+  if (!states || !actions) return bfail(bt, PAKR_E_INVALID_ARG, "null output arrays");
+  e = read_path(bt->args[q], h.best_edges, states, actions);
+  if (e != hipSuccess) return bhip_fail(bt, e, "read path");
+  return PAKR_OK;
+}
+
+int pakr_batch_grid(const pakr_batch* bt) { return bt ? bt->G : 0; }
+
+const char* pakr_batch_last_error(const pakr_batch* bt) {
+  return bt ? bt->err.c_str() : g_init_error.c_str();
+}
+
+void pakr_batch_destroy(pakr_batch* bt) {
+  if (!bt) return;
+  if (bt->ws) (void)hipStreamSynchronize(bt->stream);
+  if (bt->gexec) (void)hipGraphExecDestroy(bt->gexec);
+  if (bt->graph) (void)hipGraphDestroy(bt->graph);
+  if (bt->cap_stream) (void)hipStreamDestroy(bt->cap_stream);
+  if (bt->own_ws && bt->ws) (void)hipFree(bt->ws);
+  delete bt;
 }
 
 }  // extern "C"

@@ -64,13 +64,13 @@ __device__ __forceinline__ unsigned long long pack_key(float v, uint32_t idx) {
 // Grid-wide barrier with a bounded wait.  Workgroup 0 collects the arrival
 // flags and publishes a release word (generation << 1 | failed).  Returns
 // false if any wait timed out; every workgroup then leaves the kernel.
-__device__ __forceinline__ bool grid_barrier(const KArgs& a, uint32_t& gen, int* s_fail) {
+__device__ __forceinline__ bool grid_barrier(const KArgs& a, uint32_t& gen, int* s_fail, int wg,
+                                             int G) {
   ++gen;
   __syncthreads();
-  const int G = gridDim.x;
   if (G == 1) return true;
   const uint32_t target = gen & 0x7fffffffu;
-  if (blockIdx.x == 0) {
+  if (wg == 0) {
     if (threadIdx.x == 0) *s_fail = 0;
     __syncthreads();
     for (int i = threadIdx.x + 1; i < G; i += NT) {
@@ -97,8 +97,7 @@ __device__ __forceinline__ bool grid_barrier(const KArgs& a, uint32_t& gen, int*
   } else if (threadIdx.x == 0) {
     *s_fail = 0;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __hip_atomic_store(&a.bar_flags[blockIdx.x], target, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&a.bar_flags[wg], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const long long limit = wall_clock64() + a.barrier_timeout_ticks;
     while (true) {
       const uint32_t v = __hip_atomic_load(&a.hdr->release, __ATOMIC_RELAXED,
@@ -178,24 +177,38 @@ __device__ __forceinline__ void block_exclusive_scan(const int* cnt, int* off, i
   __syncthreads();
 }
 
+// LDS used by one query's loop; each kernel that runs plan_loop declares it.
+struct Smem {
+  float* obs;                  // dynamic: obstacles (see any_obstacle_hit)
+  float* tile;                 // [D][TILE] NN tile, 16-byte aligned
+  unsigned long long* best;    // [NT] parent keys of a rollout chunk
+  int* cnt;                    // [MAX_GR] survivors per rollout chunk
+  int* off;                    // [MAX_GR + 1] their exclusive prefix
+  int* wave;                   // [NT / WAVE]
+  float* val;                  // [VAL_FLOATS] validity constants
+  unsigned long long* goal;
+  int* fail;
+  int* misc;                   // [2]
+};
+
+// The AO-x loop of one query, run by workgroup `b` of the `G` workgroups that
+// share the query (G = 1 when a workgroup plans a query alone).
 template <int SYS, int QT>
-__global__ __launch_bounds__(NT) void k_plan(KArgs a) {
+__device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int G, const Smem& sm) {
   constexpr int D = Sys<SYS>::D, M = Sys<SYS>::M, NP = Sys<SYS>::P;
   const DevProblem& P = a.P;
-  extern __shared__ float s_obs[];
-  __shared__ __align__(16) float s_tile[D][TILE];
-  __shared__ unsigned long long s_best[NT];
-  __shared__ int s_cnt[MAX_GR];
-  __shared__ int s_off[MAX_GR + 1];
-  __shared__ int s_wave[NT / WAVE];
-  __shared__ float s_val[VAL_FLOATS];
-  __shared__ unsigned long long s_goal;
-  __shared__ int s_fail;
-  __shared__ int s_misc[2];
+  float* const s_obs = sm.obs;
+  float (*const s_tile)[TILE] = reinterpret_cast<float (*)[TILE]>(sm.tile);
+  unsigned long long* const s_best = sm.best;
+  int* const s_cnt = sm.cnt;
+  int* const s_off = sm.off;
+  int* const s_wave = sm.wave;
+  float* const s_val = sm.val;
+  unsigned long long& s_goal = *sm.goal;
+  int& s_fail = *sm.fail;
+  int* const s_misc = sm.misc;
 
   const int tid = threadIdx.x;
-  const int b = blockIdx.x;
-  const int G = gridDim.x;
   const int B = P.B, A = P.A, K = P.K, GR = P.G_roll;
   const int L = P.lanes, CPB = P.cpb;   // lanes per candidate, candidates per rollout workgroup
   const int S = GR * CPB;
@@ -340,7 +353,7 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
       __hip_atomic_store(&a.hdr->stop[it_done & 1], stop, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (!grid_barrier(a, gen, &s_fail)) {
+    if (!grid_barrier(a, gen, &s_fail, b, G)) {
       if (tid == 0) __hip_atomic_store(&a.hdr->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return;
     }
@@ -355,11 +368,12 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
     mark(1);
 
     // ---------------- phase 2: controls, rollout, validity, prune ---------
-    if (b < GR) {
-      const int j0 = b * CPB;
+    for (int rb = b; rb < GR; rb += G) {
+      const int j0 = rb * CPB;
       const int j1 = min(B, j0 + CPB);
       const int k0 = j0 / A;
       const int nql = (j1 - 1) / A - k0 + 1;
+      __syncthreads();  // the previous chunk's readers of s_best / s_goal are done
       for (int i = tid; i < nql; i += NT) s_best[i] = ~0ull;
       if (tid == 0) s_goal = ~0ull;
       __syncthreads();
@@ -469,7 +483,7 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
         total += s_wave[w];
       }
       if (keep) {
-        const int e = b * CPB + base_r + wrank;
+        const int e = rb * CPB + base_r + wrank;
 #pragma unroll
         for (int c = 0; c < D; ++c) stg_x[(size_t)c * S + e] = x[c];
 #pragma unroll
@@ -482,8 +496,8 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
       }
       __syncthreads();
       if (tid == 0) {
-        a.counts[b] = total;
-        a.goalmin[b] = s_goal;
+        a.counts[rb] = total;
+        a.goalmin[rb] = s_goal;
       }
       if (trace != nullptr && active && lead) {
         TraceView tv(trace, K, B, D, M);
@@ -497,9 +511,10 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
                       (in_goal ? F_GOAL : 0);
         tv.slots[j] = -1;
       }
+      mark(3);
     }
     mark(3);
-    if (!grid_barrier(a, gen, &s_fail)) {
+    if (!grid_barrier(a, gen, &s_fail, b, G)) {
       if (tid == 0) __hip_atomic_store(&a.hdr->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return;
     }
@@ -686,6 +701,78 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
     h->status = status | (n_sol > 0 ? PAKR_S_SOLVED : 0);
     for (int i = 0; i < 6; ++i) h->ticks[i] = tk[i];
   }
+}
+
+__device__ __forceinline__ Smem make_smem(float* obs, float* tile, unsigned long long* best, int* cnt,
+                                          int* off, int* wave, float* val,
+                                          unsigned long long* goal, int* fail, int* misc) {
+  Smem m;
+  m.obs = obs;
+  m.tile = tile;
+  m.best = best;
+  m.cnt = cnt;
+  m.off = off;
+  m.wave = wave;
+  m.val = val;
+  m.goal = goal;
+  m.fail = fail;
+  m.misc = misc;
+  return m;
+}
+
+// One query planned by the whole (cooperative) grid.
+template <int SYS, int QT>
+__global__ __launch_bounds__(NT) void k_plan(KArgs a) {
+  extern __shared__ float s_obs[];
+  __shared__ __align__(16) float s_tile[Sys<SYS>::D * TILE];
+  __shared__ unsigned long long s_best[NT];
+  __shared__ int s_cnt[MAX_GR];
+  __shared__ int s_off[MAX_GR + 1];
+  __shared__ int s_wave[NT / WAVE];
+  __shared__ float s_val[VAL_FLOATS];
+  __shared__ unsigned long long s_goal;
+  __shared__ int s_fail;
+  __shared__ int s_misc[2];
+  const Smem sm = make_smem(s_obs, s_tile, s_best, s_cnt, s_off, s_wave, s_val, &s_goal, &s_fail,
+                            s_misc);
+  plan_loop<SYS, QT>(a, blockIdx.x, gridDim.x, sm);
+}
+
+// Many queries in one launch: each workgroup takes the next query from a
+// device work queue and plans it alone (no grid barrier), until the queue is
+// empty.  Queries may mix systems and tree capacities.
+__global__ __launch_bounds__(NT) void k_batch(const KArgs* __restrict__ qs, int nq, int* queue) {
+  extern __shared__ float s_obs[];
+  __shared__ __align__(16) float s_tile[PAKR_MAX_D * TILE];
+  __shared__ unsigned long long s_best[NT];
+  __shared__ int s_cnt[MAX_GR];
+  __shared__ int s_off[MAX_GR + 1];
+  __shared__ int s_wave[NT / WAVE];
+  __shared__ float s_val[VAL_FLOATS];
+  __shared__ unsigned long long s_goal;
+  __shared__ int s_fail;
+  __shared__ int s_misc[2];
+  __shared__ int s_q;
+  const Smem sm = make_smem(s_obs, s_tile, s_best, s_cnt, s_off, s_wave, s_val, &s_goal, &s_fail,
+                            s_misc);
+  while (true) {
+    __syncthreads();  // everyone has read the previous s_q
+    if (threadIdx.x == 0) s_q = atomicAdd(queue, 1);
+    __syncthreads();
+    const int q = __builtin_amdgcn_readfirstlane(s_q);
+    if (q >= nq) break;
+    const KArgs& a = qs[q];
+    switch (a.P.system) {
+      case PAKR_DI2: plan_loop<PAKR_DI2, 1>(a, 0, 1, sm); break;
+      case PAKR_DI3: plan_loop<PAKR_DI3, 1>(a, 0, 1, sm); break;
+      case PAKR_CAR: plan_loop<PAKR_CAR, 1>(a, 0, 1, sm); break;
+      default: plan_loop<PAKR_QUAD, 1>(a, 0, 1, sm); break;
+    }
+  }
+}
+
+__global__ void k_reset_queue(int* queue) {
+  if (threadIdx.x == 0) *queue = 0;
 }
 
 // Writes the root (x_init, no action, cost 0) and resets the loop state.

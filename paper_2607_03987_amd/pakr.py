@@ -35,7 +35,11 @@ TRACE_HDR_WORDS = 16
 
 EXPORTED = ["pakr_workspace_size", "pakr_plan_init", "pakr_plan_destroy", "pakr_trace_bytes",
             "pakr_expand", "pakr_replan", "pakr_status", "pakr_solutions", "pakr_extract_path",
-            "pakr_copy_tree", "pakr_last_error", "pakr_error_string"]
+            "pakr_copy_tree", "pakr_last_error", "pakr_error_string",
+            "pakr_batch_workspace_size", "pakr_batch_init", "pakr_batch_replan",
+            "pakr_batch_graph_capture", "pakr_batch_graph_launch", "pakr_batch_status",
+            "pakr_batch_solutions", "pakr_batch_extract_path", "pakr_batch_grid",
+            "pakr_batch_last_error", "pakr_batch_destroy"]
 
 
 class PakrError(RuntimeError):
@@ -80,7 +84,8 @@ class Stats(C.Structure):
                 ("t_first_ms", C.c_double), ("t_last_ms", C.c_double), ("call_iters", C.c_int),
                 ("call_rounds", C.c_int), ("call_solutions", C.c_int), ("reserved", C.c_int),
                 ("nn_ms", C.c_double), ("rollout_ms", C.c_double), ("insert_ms", C.c_double),
-                ("step_ms", C.c_double * 6)]
+                ("step_ms", C.c_double * 6), ("clock_start_ms", C.c_double),
+                ("clock_end_ms", C.c_double)]
 
 
 class Solution(C.Structure):
@@ -129,6 +134,34 @@ def load():
         L.pakr_last_error.restype = C.c_char_p
         L.pakr_error_string.argtypes = [C.c_int]
         L.pakr_error_string.restype = C.c_char_p
+        L.pakr_batch_workspace_size.argtypes = [C.c_int, C.POINTER(System), C.POINTER(Scene),
+                                                C.POINTER(Params)]
+        L.pakr_batch_workspace_size.restype = sz
+        L.pakr_batch_init.argtypes = [C.c_int, C.POINTER(System), C.POINTER(Scene),
+                                      C.POINTER(C.POINTER(C.c_float)), C.POINTER(Goal),
+                                      C.POINTER(Params), vp, sz, vp, C.POINTER(vp)]
+        L.pakr_batch_init.restype = C.c_int
+        L.pakr_batch_replan.argtypes = [vp, C.c_double, C.c_int, C.c_longlong]
+        L.pakr_batch_replan.restype = C.c_int
+        L.pakr_batch_graph_capture.argtypes = [vp, C.c_double, C.c_int, C.c_longlong]
+        L.pakr_batch_graph_capture.restype = C.c_int
+        L.pakr_batch_graph_launch.argtypes = [vp]
+        L.pakr_batch_graph_launch.restype = C.c_int
+        L.pakr_batch_status.argtypes = [vp, C.c_int, C.POINTER(Stats)]
+        L.pakr_batch_status.restype = C.c_int
+        L.pakr_batch_solutions.argtypes = [vp, C.c_int, C.POINTER(Solution), C.c_int,
+                                           C.POINTER(C.c_int)]
+        L.pakr_batch_solutions.restype = C.c_int
+        L.pakr_batch_extract_path.argtypes = [vp, C.c_int, C.POINTER(C.c_float),
+                                              C.POINTER(C.c_float), C.c_int, C.POINTER(C.c_int),
+                                              C.POINTER(C.c_double)]
+        L.pakr_batch_extract_path.restype = C.c_int
+        L.pakr_batch_grid.argtypes = [vp]
+        L.pakr_batch_grid.restype = C.c_int
+        L.pakr_batch_last_error.argtypes = [vp]
+        L.pakr_batch_last_error.restype = C.c_char_p
+        L.pakr_batch_destroy.argtypes = [vp]
+        L.pakr_batch_destroy.restype = None
         _lib = L
     return _lib
 
@@ -332,6 +365,123 @@ class Plan:
                             controls=controls.copy(), xnew=xnew.copy(), cnew=cnew, flags=flags,
                             slots=slots))
         return out
+
+
+def _bcheck(rc: int, handle=None):
+    if rc != PAKR_OK:
+        msg = load().pakr_batch_last_error(handle)
+        raise PakrError(rc, msg.decode() if msg else "")
+
+
+class CBatch:
+    """The C arrays of a list of Problems (holds the host arrays alive)."""
+
+    def __init__(self, probs, lanes: int = 0):
+        self.probs = list(probs)
+        n = self.n = len(self.probs)
+        self.qs = [CQuery(p, lanes=lanes) for p in self.probs]
+        self.sys = (System * n)(*[q.system for q in self.qs])
+        self.sc = (Scene * n)(*[q.scene for q in self.qs])
+        self.goal = (Goal * n)(*[q.goal for q in self.qs])
+        self.prm = (Params * n)(*[q.params for q in self.qs])
+        self.x = (C.POINTER(C.c_float) * n)(*[_fp(q.x_init) for q in self.qs])
+
+
+def batch_workspace_size(cb: CBatch) -> int:
+    return int(load().pakr_batch_workspace_size(cb.n, cb.sys, cb.sc, cb.prm))
+
+
+def batch_init(cb: CBatch, d_workspace: int, ws_bytes: int, stream: int) -> int:
+    h = C.c_void_p()
+    rc = load().pakr_batch_init(cb.n, cb.sys, cb.sc, cb.x, cb.goal, cb.prm,
+                                C.c_void_p(d_workspace), ws_bytes, C.c_void_p(stream), C.byref(h))
+    _bcheck(rc, None)
+    return h.value
+
+
+class BatchPlan:
+    """Many queries planned by one persistent launch (one workgroup per query).
+
+    Query q's results equal those of Plan(probs[q], lanes=...) with the same
+    parameters; the workspace is one torch uint8 tensor.
+    """
+
+    def __init__(self, probs, lanes: int = 0, device=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("libpakr needs a ROCm GPU; none is visible")
+        self.torch = torch
+        self.cb = CBatch(probs, lanes=lanes)
+        self.probs = self.cb.probs
+        nbytes = batch_workspace_size(self.cb)
+        if nbytes == 0:
+            batch_init(self.cb, 0, 0, 0)  # reports which query is malformed
+            raise PakrError(-1, "batch_workspace_size rejected the queries")
+        self.device = torch.device(device or "cuda")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self.workspace.data_ptr() + 255) & ~255
+        self.stream = torch.cuda.current_stream(self.device)
+        self.h = batch_init(self.cb, ptr, nbytes, self.stream.cuda_stream)
+        self.n = self.cb.n
+
+    def close(self):
+        h = getattr(self, "h", None)
+        if h:
+            load().pakr_batch_destroy(h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def grid(self) -> int:
+        return int(load().pakr_batch_grid(self.h))
+
+    def replan(self, budget_ms: float = 0.0, max_rounds: int = 0, max_iters: int = 0):
+        _bcheck(load().pakr_batch_replan(self.h, float(budget_ms), int(max_rounds),
+                                         int(max_iters)), self.h)
+
+    def graph_capture(self, budget_ms: float = 0.0, max_rounds: int = 0, max_iters: int = 0):
+        _bcheck(load().pakr_batch_graph_capture(self.h, float(budget_ms), int(max_rounds),
+                                                int(max_iters)), self.h)
+
+    def graph_launch(self):
+        _bcheck(load().pakr_batch_graph_launch(self.h), self.h)
+
+    def status(self, q: int) -> dict:
+        s = Stats()
+        _bcheck(load().pakr_batch_status(self.h, q, C.byref(s)), self.h)
+        out = {f[0]: getattr(s, f[0]) for f in Stats._fields_}
+        out["step_ms"] = list(out["step_ms"])
+        return out
+
+    def solutions(self, q: int) -> list:
+        n = C.c_int(0)
+        _bcheck(load().pakr_batch_solutions(self.h, q, None, 0, C.byref(n)), self.h)
+        arr = (Solution * max(n.value, 1))()
+        _bcheck(load().pakr_batch_solutions(self.h, q, arr, n.value, C.byref(n)), self.h)
+        return [{f[0]: getattr(arr[i], f[0]) for f in Solution._fields_}
+                for i in range(min(n.value, 1024))]
+
+    def extract_path(self, q: int):
+        ne = C.c_int(0)
+        cost = C.c_double(0)
+        rc = load().pakr_batch_extract_path(self.h, q, None, None, 0, C.byref(ne), C.byref(cost))
+        if rc == -6:
+            return None
+        if rc not in (0, -7):
+            _bcheck(rc, self.h)
+        n = ne.value
+        d, m = self.probs[q].d, self.probs[q].m
+        states = np.zeros((n + 1, d), np.float32)
+        actions = np.zeros((max(n, 1), m), np.float32)
+        _bcheck(load().pakr_batch_extract_path(self.h, q, _fp(states), _fp(actions), n,
+                                               C.byref(ne), C.byref(cost)), self.h)
+        return states, actions[:n], cost.value
 
 
 # C-ABI names at module level

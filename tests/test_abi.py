@@ -47,7 +47,7 @@ int main(void) {
          sizeof(pakr_goal), sizeof(pakr_params), sizeof(pakr_stats), sizeof(pakr_solution));
   P(pakr_system, vnorm_max); P(pakr_scene, sph_r); P(pakr_params, cost_bound);
   P(pakr_params, seed); P(pakr_params, max_path_edges); P(pakr_params, lanes_per_candidate); P(pakr_params, workgroups_per_cu); P(pakr_stats, c_best);
-  P(pakr_stats, call_iters); P(pakr_stats, insert_ms); P(pakr_stats, step_ms); P(pakr_solution, t_ms);
+  P(pakr_stats, call_iters); P(pakr_stats, insert_ms); P(pakr_stats, step_ms); P(pakr_stats, clock_end_ms); P(pakr_solution, t_ms);
   return 0;
 }
 """
@@ -134,3 +134,26 @@ def test_error_strings():
     lib = pakr.load()
     for code, name in pakr.ERRORS.items():
         assert lib.pakr_error_string(code).decode() == name
+
+
+def test_batch_init_names_the_malformed_query():
+    probs = W.config_c5(n_queries=3)
+    bad = probs[1].replace(B=probs[1].B + 1)
+    cb = pakr.CBatch([probs[0], bad, probs[2]])
+    assert pakr.batch_workspace_size(cb) == 0
+    with pytest.raises(pakr.PakrError) as ei:
+        pakr.batch_init(cb, 0, 0, 0)
+    assert ei.value.code == -1 and "query 1" in str(ei.value)
+    x0 = probs[2].x_init.copy()
+    x0[0] = -5.0
+    cb2 = pakr.CBatch([probs[0], probs[1], probs[2].replace(x_init=x0)])
+    with pytest.raises(pakr.PakrError) as ei:
+        pakr.batch_init(cb2, 0, 0, 0)
+    assert ei.value.code == -2 and "query 2" in str(ei.value)
+
+
+def test_batch_workspace_size_covers_every_query():
+    probs = W.config_c5(n_queries=8)
+    total = pakr.batch_workspace_size(pakr.CBatch(probs))
+    single = sum(4 * p.n_cap * (p.d + p.m + 2) for p in probs)
+    assert total >= single
