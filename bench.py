@@ -12,6 +12,7 @@ and to converged solution, the roofline of the planner kernel and the FP64
 reference's throughput on this host's CPU.
 """
 import argparse
+import itertools
 import json
 import math
 import os
@@ -84,6 +85,77 @@ def measured_traffic():
                      float(vals["write_kib_per_dispatch"]) * float(vals["write_factor"]))
 
 
+def batched_vs_plain(torch, pakr, W, n_queries, rounds, iters_per_round, lanes=1):
+    """The mixed batch (double integrator, car, quadrotor queries with uneven
+    capacities) in one graph-launched persistent kernel, against the same
+    queries planned one at a time with the whole GPU each.  Both forms run
+    `rounds` AO-x rounds per query (deterministic), so per-query solution costs
+    must be identical; the comparison is queries/s and solve latency."""
+    probs = [p.replace(max_iters_per_round=iters_per_round)
+             for p in W.config_c5(n_queries=n_queries, seed=0)]
+    stream = torch.cuda.current_stream()
+    # batched: one launch, replayed from a captured graph
+    bp = pakr.BatchPlan(probs, lanes=lanes)
+    bp.graph_capture(max_rounds=rounds)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    bp.graph_launch()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    batch_wall = time.perf_counter() - t0
+    batch_ms = e0.elapsed_time(e1)
+    bst = [bp.status(q) for q in range(len(probs))]
+    b_sols = [bp.solutions(q) for q in range(len(probs))]
+    t_base = min(s["clock_start_ms"] for s in bst)
+    b_done = [s["clock_end_ms"] - t_base for s in bst]
+    b_first = [s["clock_start_ms"] - t_base + s["t_first_ms"] for s in bst if s["t_first_ms"] >= 0]
+    # plain: the same queries one at a time, each with the whole GPU
+    plans = [pakr.Plan(p) for p in probs]
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in plans]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p, (a, b) in zip(plans, ev):
+        a.record(stream)
+        p.replan(max_rounds=rounds)
+        b.record(stream)
+    torch.cuda.synchronize()
+    plain_wall = time.perf_counter() - t0
+    p_ms = [a.elapsed_time(b) for a, b in ev]
+    pst = [p.status() for p in plans]
+    p_sols = [p.solutions() for p in plans]
+    p_cum = list(itertools.accumulate(p_ms))
+    p_first = [sum(p_ms[:q]) + s["t_first_ms"] for q, s in enumerate(pst) if s["t_first_ms"] >= 0]
+    same = sum(1 for a, b in zip(b_sols, p_sols)
+               if [(x["round"], x["iter"], x["node"], x["cost"]) for x in a] ==
+               [(x["round"], x["iter"], x["node"], x["cost"]) for x in b])
+    pct = lambda v, q: float(statistics.quantiles(v, n=100)[q - 1]) if len(v) >= 2 else None
+    for p in plans:
+        p.close()
+    bp.close()
+    return {
+        "workload": f"{n_queries} mixed queries (3D double integrator / car / quadrotor, tree "
+                    f"capacities log-uniform in [4096, 262144], 10-60 obstacles), "
+                    f"{rounds} AO-x rounds each, at most {iters_per_round} iterations per round",
+        "batched": {"queries_per_s": n_queries / (batch_ms / 1e3), "makespan_ms": batch_ms,
+                    "wall_ms": batch_wall * 1e3, "grid": bst[0]["grid"],
+                    "p50_done_ms": pct(b_done, 50), "p99_done_ms": pct(b_done, 99),
+                    "p50_first_ms": pct(b_first, 50), "p99_first_ms": pct(b_first, 99),
+                    "expansions": sum(s["expansions"] for s in bst)},
+        "plain": {"queries_per_s": n_queries / (sum(p_ms) / 1e3), "total_ms": sum(p_ms),
+                  "wall_ms": plain_wall * 1e3,
+                  "p50_alone_ms": pct(p_ms, 50), "p99_alone_ms": pct(p_ms, 99),
+                  "p50_queued_done_ms": pct(p_cum, 50), "p99_queued_done_ms": pct(p_cum, 99),
+                  "p50_queued_first_ms": pct(p_first, 50), "p99_queued_first_ms": pct(p_first, 99),
+                  "expansions": sum(s["expansions"] for s in pst)},
+        "speedup_queries_per_s": sum(p_ms) / batch_ms,
+        "queries_with_identical_solutions": f"{same}/{n_queries}",
+        "solved": f"{sum(1 for x in b_sols if x)}/{n_queries}",
+    }
+
+
 def cpu_baseline(prob, seconds):
     """Time the FP64 reference (single thread) on the same query for ~`seconds`."""
     import oracle
@@ -112,6 +184,10 @@ def main():
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--wg-per-cu", type=int, default=0)
     ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--batch-queries", type=int, default=256)
+    ap.add_argument("--batch-rounds", type=int, default=2)
+    ap.add_argument("--batch-iters-per-round", type=int, default=50)
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before timing, run one plain device copy of this size (a known-size "
                          "kernel against which HBM counters are scaled)")
@@ -228,10 +304,13 @@ def main():
         "cpu_baseline": None,
         "batched": None,
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(W.config_c2(seed=0), args.cpu_seconds)
     for p in plans:
         p.close()
+    if not args.no_batched:
+        out["batched"] = batched_vs_plain(torch, pakr, W, args.batch_queries, args.batch_rounds,
+                                          args.batch_iters_per_round)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(W.config_c2(seed=0), args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

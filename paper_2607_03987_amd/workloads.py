@@ -268,9 +268,10 @@ def config_c5(n_queries: int = 256, seed: int = 0, systems=(DI3, CAR, QUAD),
               settings: Optional[dict] = None) -> List[Problem]:
     """Mixed batch: query q uses systems[q % len(systems)], random start/goal/scene.
 
-    Tree capacities are log-uniform in [4096, 262144] rounded up to 64; 10..60
-    obstacles per scene; start and goal at least 1 from the walls and at least
-    half the workspace side apart.
+    Tree capacities are log-uniform in [4096, 262144] rounded up to 64, and at
+    least one batch plus the root (B + 1, rounded up to 64); 10..60 obstacles per
+    scene; start and goal at least 1 from the walls and at least half the
+    workspace side apart.
     """
     out = []
     for q in range(n_queries):
@@ -302,6 +303,7 @@ def config_c5(n_queries: int = 256, seed: int = 0, systems=(DI3, CAR, QUAD),
         kw = dict(_BATCH_SETTINGS[system])
         if settings and system in settings:
             kw.update(settings[system])
+        cap = max(cap, (kw["B"] + 1 + 63) // 64 * 64)
         kw.update(n_cap=cap, cost_kind=COST_DURATION, seed=seed, qid=q,
                   name=f"c5_q{q}_{SYSTEM_NAMES[system]}")
         out.append(build_problem(system, ws_lo, ws_hi, *scene, x0, g, goal_r, **kw))
