@@ -85,14 +85,14 @@ def measured_traffic():
                      float(vals["write_kib_per_dispatch"]) * float(vals["write_factor"]))
 
 
-def batched_vs_plain(torch, pakr, W, n_queries, rounds, iters_per_round, lanes=1):
+def batched_vs_plain(torch, pakr, W, n_queries, rounds, iters_per_round, lanes=1, settings=None):
     """The mixed batch (double integrator, car, quadrotor queries with uneven
     capacities) in one graph-launched persistent kernel, against the same
     queries planned one at a time with the whole GPU each.  Both forms run
     `rounds` AO-x rounds per query (deterministic), so per-query solution costs
     must be identical; the comparison is queries/s and solve latency."""
     probs = [p.replace(max_iters_per_round=iters_per_round)
-             for p in W.config_c5(n_queries=n_queries, seed=0)]
+             for p in W.config_c5(n_queries=n_queries, seed=0, settings=settings)]
     stream = torch.cuda.current_stream()
     # batched: one launch, replayed from a captured graph
     bp = pakr.BatchPlan(probs, lanes=lanes)
@@ -150,6 +150,8 @@ def batched_vs_plain(torch, pakr, W, n_queries, rounds, iters_per_round, lanes=1
                   "p50_queued_done_ms": pct(p_cum, 50), "p99_queued_done_ms": pct(p_cum, 99),
                   "p50_queued_first_ms": pct(p_first, 50), "p99_queued_first_ms": pct(p_first, 99),
                   "expansions": sum(s["expansions"] for s in pst)},
+        "settings": {W.SYSTEM_NAMES[k]: v for k, v in (settings or {}).items()},
+        "lanes": lanes,
         "speedup_queries_per_s": sum(p_ms) / batch_ms,
         "queries_with_identical_solutions": f"{same}/{n_queries}",
         "solved": f"{sum(1 for x in b_sols if x)}/{n_queries}",
@@ -199,7 +201,7 @@ def main():
 
     import torch
 
-    from paper_2607_03987_amd import _build, pakr, workloads as W
+    from paper_2607_03987_amd import _build, autotune, pakr, workloads as W
 
     if not os.path.exists(pakr.LIB_PATH):
         _build.build(force=True)
@@ -214,7 +216,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    mk = lambda pr: pakr.Plan(pr, grid=args.grid, lanes=args.lanes, wg_per_cu=args.wg_per_cu)
+    tuned = autotune.load_table()
+    lanes = args.lanes or int(tuned.get("single", {}).get("lanes", 0))
+    wgpc = args.wg_per_cu or int(tuned.get("single", {}).get("workgroups_per_cu", 0))
+    mk = lambda pr: pakr.Plan(pr, grid=args.grid, lanes=lanes, wg_per_cu=wgpc)
     warm = [mk(W.config_c2(seed=10_000 + i)) for i in range(args.warmup)]
     for p in warm:
         p.replan(budget_ms=args.budget_ms)
@@ -277,7 +282,8 @@ def main():
                                "U(0.5,2.5), start (1,1,1), goal ball (9,9,9) r 0.5, duration cost",
                    "B": prob.B, "A": prob.A, "K": prob.K, "T": prob.T, "dt": float(prob.dt),
                    "n_cap": prob.n_cap, "budget_ms": args.budget_ms,
-                   "seeds": f"0..{args.steps - 1}", "grid": stats[0]["grid"], "device": dev_name},
+                   "seeds": f"0..{args.steps - 1}", "grid": stats[0]["grid"],
+                   "lanes_per_candidate": lanes or "auto", "device": dev_name},
         "time_to_first_ms_median": med(t_first),
         "time_to_converged_ms_median": med(t_conv),
         "cost_first_median": med(c_first),
@@ -308,7 +314,9 @@ def main():
         p.close()
     if not args.no_batched:
         out["batched"] = batched_vs_plain(torch, pakr, W, args.batch_queries, args.batch_rounds,
-                                          args.batch_iters_per_round)
+                                          args.batch_iters_per_round,
+                                          lanes=autotune.batch_lanes(tuned),
+                                          settings=autotune.batch_settings(tuned))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W.config_c2(seed=0), args.cpu_seconds)
     print(json.dumps(out), flush=True)
