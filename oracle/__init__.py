@@ -59,6 +59,12 @@ class _Problem(C.Structure):
     ]
 
 
+class _Refine(C.Structure):
+    _fields_ = [("w_u", C.c_double), ("w_g", C.c_double), ("w_c", C.c_double),
+                ("beta", C.c_double), ("delta", C.c_double), ("u_ref", C.c_double * 4),
+                ("u_scale", C.c_double * 4)]
+
+
 class _Steer(C.Structure):
     _fields_ = [("parents", _ip), ("flags", _ip), ("goal_j", C.c_int)]
 
@@ -131,6 +137,10 @@ def lib():
         L.orc_plan_solutions.restype = C.c_int
         L.orc_plan_best_path.argtypes = [vp, _dp, _dp, C.c_int, _ip, _dp]
         L.orc_plan_best_path.restype = C.c_int
+        L.orc_traj_cost.argtypes = [C.POINTER(_Problem), C.POINTER(_Refine), _dp, _dp, C.c_int]
+        L.orc_traj_cost.restype = C.c_double
+        L.orc_traj_grad.argtypes = [C.POINTER(_Problem), C.POINTER(_Refine), _dp, _dp, C.c_int,
+                                    _dp]
         _lib = L
     return _lib
 
@@ -380,3 +390,32 @@ class OraclePlan:
         lib().orc_plan_best_path(self.h, _ptr(states, C.c_double), _ptr(actions, C.c_double), n,
                                  C.byref(ne), C.byref(cost))
         return states, actions[:n], cost.value
+
+
+# ---------------------------------------------------------------------------
+# trajectory refinement objective (complex-step gradient)
+# ---------------------------------------------------------------------------
+
+def refine_params(w_u, w_g, w_c, beta, delta, u_ref, u_scale):
+    r = _Refine(w_u=w_u, w_g=w_g, w_c=w_c, beta=beta, delta=delta)
+    for i in range(len(u_ref)):
+        r.u_ref[i] = float(u_ref[i])
+        r.u_scale[i] = float(u_scale[i])
+    for i in range(len(u_ref), 4):
+        r.u_scale[i] = 1.0
+    return r
+
+
+def traj_cost(cp: CProblem, rp, x0, U) -> float:
+    x0, U = _d(x0), _d(U)
+    M = U.shape[0]
+    return lib().orc_traj_cost(cp.ref, C.byref(rp), _ptr(x0, C.c_double), _ptr(U, C.c_double), M)
+
+
+def traj_grad(cp: CProblem, rp, x0, U) -> np.ndarray:
+    x0, U = _d(x0), _d(U)
+    M = U.shape[0]
+    g = np.zeros_like(U)
+    lib().orc_traj_grad(cp.ref, C.byref(rp), _ptr(x0, C.c_double), _ptr(U, C.c_double), M,
+                        _ptr(g, C.c_double))
+    return g

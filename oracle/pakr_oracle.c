@@ -780,3 +780,164 @@ int orc_plan_best_path(const orc_plan* pl, double* states, double* actions, int 
   if (actions) memcpy(actions, pl->best_actions, sizeof(double) * (size_t)pl->best_edges * m);
   return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Trajectory refinement objective, evaluated in complex arithmetic so that  */
+/* the complex-step method gives its exact gradient.  For a real input the   */
+/* imaginary parts stay zero and this is the plain FP64 objective.  The      */
+/* dynamics are written again here over complex numbers (no shared code      */
+/* with the real-valued planner functions above).                           */
+/* ------------------------------------------------------------------------ */
+#include <complex.h>
+
+typedef double complex cplx;
+
+/* branch on the real part, keep the derivative of the active branch */
+static cplx c_abs(cplx z) { return creal(z) >= 0.0 ? z : -z; }
+static cplx c_max(cplx a, cplx b) { return creal(a) >= creal(b) ? a : b; }
+static cplx c_min(cplx a, cplx b) { return creal(a) <= creal(b) ? a : b; }
+
+static cplx c_softplus(cplx z, double beta) {
+  /* log(1 + exp(beta z)) / beta, evaluated without overflow */
+  cplx bz = beta * z;
+  if (creal(bz) > 0.0) return (bz + clog(1.0 + cexp(-bz))) / beta;
+  return clog(1.0 + cexp(bz)) / beta;
+}
+
+static void c_dynamics(const orc_problem* p, const cplx* x, const cplx* u, cplx* xd) {
+  if (p->system == ORC_DI2 || p->system == ORC_DI3) {
+    int D = p->npos;
+    for (int a = 0; a < D; ++a) {
+      xd[a] = x[D + a];
+      xd[D + a] = u[a];
+    }
+  } else if (p->system == ORC_CAR) {
+    double L = (double)p->dyn[0];
+    xd[0] = x[3] * ccos(x[2]);
+    xd[1] = x[3] * csin(x[2]);
+    xd[2] = x[3] * ctan(x[4]) / L;
+    xd[3] = u[0];
+    xd[4] = u[1];
+  } else {
+    double mass = p->dyn[0], g = p->dyn[1], Ix = p->dyn[2], Iy = p->dyn[3], Iz = p->dyn[4];
+    cplx cph = ccos(x[3]), sph = csin(x[3]), cth = ccos(x[4]), sth = csin(x[4]);
+    cplx cps = ccos(x[5]), sps = csin(x[5]);
+    cplx R[3][3] = {{cps * cth, cps * sth * sph - sps * cph, cps * sth * cph + sps * sph},
+                    {sps * cth, sps * sth * sph + cps * cph, sps * sth * cph - cps * sph},
+                    {-sth, cth * sph, cth * cph}};
+    cplx v[3] = {x[6], x[7], x[8]}, w[3] = {x[9], x[10], x[11]};
+    for (int i = 0; i < 3; ++i) xd[i] = R[i][0] * v[0] + R[i][1] * v[1] + R[i][2] * v[2];
+    cplx a = w[1] * sph + w[2] * cph;
+    xd[3] = w[0] + a * sth / cth;
+    xd[4] = w[1] * cph - w[2] * sph;
+    xd[5] = a / cth;
+    cplx wxv[3] = {w[1] * v[2] - w[2] * v[1], w[2] * v[0] - w[0] * v[2], w[0] * v[1] - w[1] * v[0]};
+    for (int i = 0; i < 3; ++i) xd[6 + i] = -wxv[i] - g * R[2][i];
+    xd[8] += u[0] / mass;
+    xd[9] = (u[1] - (Iz - Iy) * w[1] * w[2]) / Ix;
+    xd[10] = (u[2] - (Ix - Iz) * w[2] * w[0]) / Iy;
+    xd[11] = (u[3] - (Iy - Ix) * w[0] * w[1]) / Iz;
+  }
+}
+
+static void c_rk4(const orc_problem* p, cplx* x, const cplx* u, double h) {
+  int d = p->d;
+  cplx k1[MAXD], k2[MAXD], k3[MAXD], k4[MAXD], t[MAXD];
+  c_dynamics(p, x, u, k1);
+  for (int i = 0; i < d; ++i) t[i] = x[i] + 0.5 * h * k1[i];
+  c_dynamics(p, t, u, k2);
+  for (int i = 0; i < d; ++i) t[i] = x[i] + 0.5 * h * k2[i];
+  c_dynamics(p, t, u, k3);
+  for (int i = 0; i < d; ++i) t[i] = x[i] + h * k3[i];
+  c_dynamics(p, t, u, k4);
+  for (int i = 0; i < d; ++i) x[i] = x[i] + h / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+}
+
+/* smooth penalty of one state: obstacles, workspace, limits, speed norm */
+static cplx c_state_penalty(const orc_problem* p, const orc_refine* rp, const cplx* x) {
+  int P = p->npos;
+  double beta = rp->beta;
+  cplx pen = 0.0;
+  for (int b = 0; b < p->n_box; ++b) {
+    cplx q[3], outside = 0.0, inner = -INFINITY;
+    for (int c = 0; c < P; ++c) {
+      q[c] = c_abs(x[c] - (double)p->box_c[b * P + c]) - (double)p->box_h[b * P + c];
+      cplx qp = c_max(q[c], 0.0);
+      outside += qp * qp;
+      inner = c == 0 ? q[c] : c_max(inner, q[c]);
+    }
+    cplx sd = (creal(outside) > 0.0 ? csqrt(outside) : 0.0) + c_min(inner, 0.0);
+    pen += c_softplus(rp->delta - sd, beta);
+  }
+  for (int s = 0; s < p->n_sph; ++s) {
+    cplx r2 = 0.0;
+    for (int c = 0; c < P; ++c) {
+      cplx e = x[c] - (double)p->sph_c[s * P + c];
+      r2 += e * e;
+    }
+    pen += c_softplus(rp->delta - (csqrt(r2) - (double)p->sph_r[s]), beta);
+  }
+  for (int c = 0; c < P; ++c) {
+    pen += c_softplus(x[c] - (double)p->ws_hi[c], beta);
+    pen += c_softplus((double)p->ws_lo[c] - x[c], beta);
+  }
+  for (int i = P; i < p->d; ++i) {
+    if (!isinf(p->lim_hi[i])) pen += c_softplus(x[i] - (double)p->lim_hi[i], beta);
+    if (!isinf(p->lim_lo[i])) pen += c_softplus((double)p->lim_lo[i] - x[i], beta);
+  }
+  if (p->vnorm_max > 0.0f) {
+    cplx v2 = 0.0;
+    for (int c = 0; c < P; ++c) v2 += x[P + c] * x[P + c];
+    pen += c_softplus(csqrt(v2) - (double)p->vnorm_max, beta);
+  }
+  return pen;
+}
+
+static cplx c_traj_cost(const orc_problem* p, const orc_refine* rp, const double* x0,
+                        const cplx* U, int M) {
+  int d = p->d, m = p->m, P = p->npos;
+  double h = (double)p->dt, edge_t = (double)p->T * h;
+  cplx x[MAXD];
+  for (int i = 0; i < d; ++i) x[i] = x0[i];
+  cplx J = 0.0;
+  for (int e = 0; e < M; ++e) {
+    const cplx* u = U + (size_t)e * m;
+    for (int c = 0; c < m; ++c) {
+      cplx z = (u[c] - rp->u_ref[c]) / rp->u_scale[c];
+      J += rp->w_u * edge_t * z * z;
+    }
+    for (int t = 0; t < p->T; ++t) {
+      c_rk4(p, x, u, h);
+      J += rp->w_c * c_state_penalty(p, rp, x);
+    }
+  }
+  for (int c = 0; c < P; ++c) {
+    cplx e = x[c] - (double)p->goal_c[c];
+    J += rp->w_g * e * e;
+  }
+  return J;
+}
+
+double orc_traj_cost(const orc_problem* p, const orc_refine* rp, const double* x0,
+                     const double* U, int M) {
+  int n = M * p->m;
+  cplx* Uc = (cplx*)malloc(sizeof(cplx) * (size_t)(n ? n : 1));
+  for (int i = 0; i < n; ++i) Uc[i] = U[i];
+  double J = creal(c_traj_cost(p, rp, x0, Uc, M));
+  free(Uc);
+  return J;
+}
+
+void orc_traj_grad(const orc_problem* p, const orc_refine* rp, const double* x0,
+                   const double* U, int M, double* grad) {
+  const double hstep = 1e-30;
+  int n = M * p->m;
+  cplx* Uc = (cplx*)malloc(sizeof(cplx) * (size_t)(n ? n : 1));
+  for (int i = 0; i < n; ++i) Uc[i] = U[i];
+  for (int i = 0; i < n; ++i) {
+    Uc[i] = U[i] + I * hstep;
+    grad[i] = cimag(c_traj_cost(p, rp, x0, Uc, M)) / hstep;
+    Uc[i] = U[i];
+  }
+  free(Uc);
+}

@@ -148,6 +148,29 @@ int orc_plan_solutions(const orc_plan* pl, orc_solution* out, int cap);
 int orc_plan_best_path(const orc_plan* pl, double* states, double* actions, int cap_edges,
                        int* n_edges, double* cost);
 
+/* --- trajectory refinement objective ----------------------------------
+ * A trajectory holds control U[e] (e < M) for T steps of dt each from x0.
+ * J = w_u * sum_e T*dt * sum_c ((U[e][c] - u_ref[c]) / u_scale[c])^2
+ *   + w_g * |pos(x_N) - goal|^2
+ *   + w_c * sum_{n=1..N} [ sum_obstacles sp(delta - sd(pos(x_n)))
+ *                          + sum_{bounded dims} sp(x - hi) + sp(lo - x)
+ *                          + (double integrators) sp(|v| - vmax) ]
+ * with N = M*T, sp(z) = log(1 + exp(beta z)) / beta and sd the signed
+ * distance to a sphere (|p-c| - r) or a box (outside: |max(|p-c|-h, 0)|;
+ * inside: max_i(|p-c|_i - h_i)); the workspace box counts as bounds on the
+ * position dimensions. */
+typedef struct {
+  double w_u, w_g, w_c, beta, delta;
+  double u_ref[4], u_scale[4];
+} orc_refine;
+
+double orc_traj_cost(const orc_problem* p, const orc_refine* rp, const double* x0,
+                     const double* U, int M);
+/* dJ/dU by the complex-step method (step 1e-30): exact to rounding, and
+ * independent of any adjoint. */
+void orc_traj_grad(const orc_problem* p, const orc_refine* rp, const double* x0,
+                   const double* U, int M, double* grad);
+
 #ifdef __cplusplus
 }
 #endif

@@ -308,3 +308,33 @@ def config_c5(n_queries: int = 256, seed: int = 0, systems=(DI3, CAR, QUAD),
                   name=f"c5_q{q}_{SYSTEM_NAMES[system]}")
         out.append(build_problem(system, ws_lo, ws_hi, *scene, x0, g, goal_r, **kw))
     return out
+
+
+@dataclasses.dataclass(frozen=True)
+class RefineSettings:
+    """Weights of the trajectory refinement objective (inputs, not arithmetic).
+
+    Effort is measured from the middle of the control box (hover thrust for the
+    quadrotor) in units of the box's half-range; beta = 20, delta = 0.1,
+    w_c = w_g = 10, w_u = 1; 50 Adam steps of 1e-2 in the normalised controls.
+    """
+    w_u: float
+    w_g: float
+    w_c: float
+    beta: float
+    delta: float
+    u_ref: tuple
+    u_scale: tuple
+    steps: int = 50
+    lr: float = 1e-2
+
+
+def refine_settings(prob: Problem, **over) -> RefineSettings:
+    lo = np.asarray(prob.u_lo, np.float64)[:prob.m]
+    hi = np.asarray(prob.u_hi, np.float64)[:prob.m]
+    mid = [float(np.float32(v)) for v in 0.5 * (lo + hi)]
+    half = [float(np.float32(v)) for v in 0.5 * (hi - lo)]
+    kw = dict(w_u=1.0, w_g=10.0, w_c=10.0, beta=20.0, delta=0.1, u_ref=tuple(mid),
+              u_scale=tuple(half))
+    kw.update(over)
+    return RefineSettings(**kw)
