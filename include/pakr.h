@@ -306,6 +306,91 @@ const char* pakr_batch_last_error(const pakr_batch* batch);
 
 void pakr_batch_destroy(pakr_batch* batch);
 
+/* ---------------------------------------------------------------------------
+ * Trajectory refinement (extension of the planner's output; the paper notes
+ * only that a differentiable simulator could be used this way).  A path is a
+ * start state and M piecewise-constant controls, each held for one edge of T
+ * RK4 steps of dt (Sec. IV-A).  Its smooth objective is
+ *
+ *   J(U) = w_effort    * sum_e T*dt * sum_c ((u_e,c - u_ref_c) / u_scale_c)^2
+ *        + w_goal      * |pos(x_N) - goal centre|^2
+ *        + w_collision * sum_{n=1..N} pen(x_n),          N = M*T,
+ *
+ * where pen(x) sums softplus_beta(delta - sd) over the obstacles (sd: signed
+ * distance of the position to the box or sphere) and softplus_beta of the
+ * violation of the workspace box, of every finite state limit and of the
+ * speed bound, softplus_beta(z) = log(1 + exp(beta z)) / beta.
+ * pakr_rollout_fwd evaluates J and stores the N+1 states; pakr_rollout_bwd is
+ * its hand-written reverse (adjoint) through the RK4 stages; pakr_check_path
+ * is the planner's own hard acceptance test of a path.
+ *
+ * Device arrays, many trajectories per call (one workgroup each):
+ *   x0 [n][d], U [n][M][m], J [n], gJ [n], gU [n][M][m], ok [n], cost [n],
+ *   ckpt: pakr_rollout_ckpt_bytes(r, n, M) bytes, 256-byte aligned.
+ * ------------------------------------------------------------------------- */
+typedef struct pakr_refine_params {
+  float w_effort;                  /* >= 0 */
+  float w_goal;                    /* >= 0 */
+  float w_collision;               /* >= 0 */
+  float beta;                      /* softplus sharpness, > 0 */
+  float delta;                     /* obstacle clearance margin, >= 0 */
+  float u_ref[PAKR_MAX_M];         /* effort reference control */
+  float u_scale[PAKR_MAX_M];       /* effort scale per control, > 0 */
+} pakr_refine_params;
+
+typedef struct pakr_refiner pakr_refiner;
+
+/* Validate and upload one scene for refinement: sys, scene and goal as for
+ * pakr_plan_init; of params only T, dt and cost_kind are read.  The library
+ * allocates the (small) obstacle buffer.  Enqueues on `stream`. */
+int pakr_refiner_init(const pakr_system* sys, const pakr_scene* scene, const pakr_goal* goal,
+                      const pakr_params* params, const pakr_refine_params* refine, void* stream,
+                      pakr_refiner** out);
+
+/* Replace the objective's weights (e.g. for a continuation in beta). */
+int pakr_refiner_set_params(pakr_refiner* r, const pakr_refine_params* refine);
+
+/* Checkpoint bytes for n trajectories of M edges: (M*T + 1) * d floats each.
+ * 0 if invalid. */
+size_t pakr_rollout_ckpt_bytes(const pakr_refiner* r, int n, int M);
+
+/* J of n trajectories; writes the states x_0..x_N of each into d_ckpt.  Async. */
+int pakr_rollout_fwd(pakr_refiner* r, int n, int M, const float* d_x0, const float* d_U,
+                     void* d_ckpt, size_t ckpt_bytes, float* d_J);
+
+/* gU = gJ * dJ/dU, reading the checkpoints that pakr_rollout_fwd wrote for
+ * the same U.  Async. */
+int pakr_rollout_bwd(pakr_refiner* r, int n, int M, const float* d_U, const void* d_ckpt,
+                     size_t ckpt_bytes, const float* d_gJ, float* d_gU);
+
+/* One projected Adam step (moments d_m1, d_m2 of n*M*m floats, zero before
+ * step 1; step counts from 1) taken in the controls normalised to [-1, 1] by
+ * the control box, then clipped to the box.  Async. */
+int pakr_refine_step(pakr_refiner* r, int n, int M, float* d_U, const float* d_gU, float* d_m1,
+                     float* d_m2, int step, float lr);
+
+/* Device bytes of the pakr_refine_paths workspace for n paths of M edges. */
+size_t pakr_refine_workspace_size(const pakr_refiner* r, int n, int M);
+
+/* Refine n paths in place: `steps` iterations of [J and its adjoint at U;
+ * trial = projected Adam step (as pakr_refine_step, with a per-path step
+ * size); J of the trial; the trial replaces U only if it lowers J, and the
+ * path's step size then grows by 1.25 (up to lr) -- otherwise it halves].
+ * J therefore never increases.  d_U [n][M][m] is read and overwritten;
+ * d_J_before / d_J_after [n] (nullable) receive J before and after.
+ * d_ws: pakr_refine_workspace_size bytes, 256-byte aligned.  Async. */
+int pakr_refine_paths(pakr_refiner* r, int n, int M, const float* d_x0, float* d_U, int steps,
+                      float lr, void* d_ws, size_t ws_bytes, float* d_J_before, float* d_J_after);
+
+/* The planner's acceptance test of each path: ok bit 0 = every sub-step
+ * state valid (workspace, limits, obstacles), bit 1 = final position in the
+ * goal ball; cost = the path's cost under cost_kind.  Async. */
+int pakr_check_path(pakr_refiner* r, int n, int M, const float* d_x0, const float* d_U,
+                    int* d_ok, float* d_cost);
+
+const char* pakr_refiner_last_error(const pakr_refiner* r);
+void pakr_refiner_destroy(pakr_refiner* r);
+
 /* Static name of an error code. */
 const char* pakr_error_string(int code);
 

@@ -10,7 +10,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpakr.so")
 SOURCES = [os.path.join(CSRC, "pakr.hip")]
-DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("pakr_device.hpp", "pakr_kernels.hpp")] + [
+DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("pakr_device.hpp", "pakr_kernels.hpp",
+                                                  "pakr_adjoint.hpp")] + [
     os.path.join(ROOT, "include", "pakr.h")]
 
 HIPFLAGS = [

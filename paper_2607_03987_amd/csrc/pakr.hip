@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "pakr_adjoint.hpp"
 #include "pakr_kernels.hpp"
 
 using namespace pakr;
@@ -127,11 +128,8 @@ bool host_state_ok(const pakr_system& s, const pakr_scene& sc, const float* x) {
   return true;
 }
 
-// Returns an empty string when the query is well formed.
-std::string validate(const pakr_system* s, const pakr_scene* sc, const float* x0,
-                     const pakr_goal* g, const pakr_params* p, int* code) {
-  *code = PAKR_E_INVALID_ARG;
-  if (!s || !sc || !x0 || !g || !p) return "null argument";
+// System record checks (and the scene's position dimension).
+std::string validate_system(const pakr_system* s, const pakr_scene* sc) {
   if (s->id < PAKR_DI2 || s->id > PAKR_QUAD) return "unknown system id";
   if (s->d != sys_d(s->id) || s->m != sys_m(s->id)) return "d/m do not match the system";
   if (sc->npos != sys_npos(s->id)) return "scene npos does not match the system";
@@ -154,6 +152,46 @@ std::string validate(const pakr_system* s, const pakr_scene* sc, const float* x0
   if (s->id == PAKR_QUAD && !(s->dyn[0] > 0.0f && s->dyn[2] > 0.0f && s->dyn[3] > 0.0f &&
                              s->dyn[4] > 0.0f && std::isfinite(s->dyn[1])))
     return "quadrotor mass and inertia must be > 0";
+  return std::string();
+}
+
+// Workspace box and obstacle records.
+std::string validate_scene(const pakr_scene* sc) {
+  const int P = sc->npos;
+  for (int c = 0; c < P; ++c)
+    if (!finite_f(sc->ws_lo[c]) || !finite_f(sc->ws_hi[c]) || !(sc->ws_lo[c] < sc->ws_hi[c]))
+      return "bad workspace box";
+  if (sc->n_box < 0 || sc->n_sphere < 0) return "negative obstacle count";
+  if (sc->n_box + sc->n_sphere > PAKR_MAX_OBSTACLES) return "too many obstacles";
+  if (sc->n_box > 0 && (!sc->box_c || !sc->box_h)) return "null box arrays";
+  if (sc->n_sphere > 0 && (!sc->sph_c || !sc->sph_r)) return "null sphere arrays";
+  for (int i = 0; i < sc->n_box * P; ++i)
+    if (!finite_f(sc->box_c[i]) || !(sc->box_h[i] > 0.0f) || !finite_f(sc->box_h[i]))
+      return "bad box";
+  for (int i = 0; i < sc->n_sphere; ++i) {
+    if (!(sc->sph_r[i] > 0.0f) || !finite_f(sc->sph_r[i])) return "bad sphere radius";
+    for (int c = 0; c < P; ++c)
+      if (!finite_f(sc->sph_c[i * P + c])) return "bad sphere centre";
+  }
+  return std::string();
+}
+
+// Goal ball inside the workspace (Sec. III).
+std::string validate_goal(const pakr_goal* g, const pakr_scene* sc) {
+  if (!(g->radius > 0.0f) || !finite_f(g->radius)) return "goal radius must be > 0";
+  for (int c = 0; c < sc->npos; ++c)
+    if (!(g->center[c] >= sc->ws_lo[c] && g->center[c] <= sc->ws_hi[c]))
+      return "goal centre outside the workspace";
+  return std::string();
+}
+
+// Returns an empty string when the query is well formed.
+std::string validate(const pakr_system* s, const pakr_scene* sc, const float* x0,
+                     const pakr_goal* g, const pakr_params* p, int* code) {
+  *code = PAKR_E_INVALID_ARG;
+  if (!s || !sc || !x0 || !g || !p) return "null argument";
+  std::string m = validate_system(s, sc);
+  if (!m.empty()) return m;
   if (p->A < 1 || p->B < 1 || p->B > PAKR_MAX_B) return "B must be in [1, 65536], A >= 1";
   if (p->B % p->A != 0) return "B must be a multiple of A";
   if (p->T < 1) return "T must be >= 1";
@@ -174,27 +212,11 @@ std::string validate(const pakr_system* s, const pakr_scene* sc, const float* x0
       p->lanes_per_candidate != 4 && p->lanes_per_candidate != 8)
     return "lanes_per_candidate must be 0, 1, 2, 4 or 8";
   if (p->workgroups_per_cu < 0 || p->workgroups_per_cu > 8) return "workgroups_per_cu must be 0..8";
-  const int P = sc->npos;
-  for (int c = 0; c < P; ++c)
-    if (!finite_f(sc->ws_lo[c]) || !finite_f(sc->ws_hi[c]) || !(sc->ws_lo[c] < sc->ws_hi[c]))
-      return "bad workspace box";
-  if (sc->n_box < 0 || sc->n_sphere < 0) return "negative obstacle count";
-  if (sc->n_box + sc->n_sphere > PAKR_MAX_OBSTACLES) return "too many obstacles";
-  if (sc->n_box > 0 && (!sc->box_c || !sc->box_h)) return "null box arrays";
-  if (sc->n_sphere > 0 && (!sc->sph_c || !sc->sph_r)) return "null sphere arrays";
-  for (int i = 0; i < sc->n_box * P; ++i)
-    if (!finite_f(sc->box_c[i]) || !(sc->box_h[i] > 0.0f) || !finite_f(sc->box_h[i]))
-      return "bad box";
-  for (int i = 0; i < sc->n_sphere; ++i) {
-    if (!(sc->sph_r[i] > 0.0f) || !finite_f(sc->sph_r[i])) return "bad sphere radius";
-    for (int c = 0; c < P; ++c)
-      if (!finite_f(sc->sph_c[i * P + c])) return "bad sphere centre";
-  }
+  m = validate_scene(sc);
+  if (!m.empty()) return m;
   *code = PAKR_E_GOAL_INVALID;
-  if (!(g->radius > 0.0f) || !finite_f(g->radius)) return "goal radius must be > 0";
-  for (int c = 0; c < P; ++c)
-    if (!(g->center[c] >= sc->ws_lo[c] && g->center[c] <= sc->ws_hi[c]))
-      return "goal centre outside the workspace";
+  m = validate_goal(g, sc);
+  if (!m.empty()) return m;
   *code = PAKR_E_START_INVALID;
   if (!host_state_ok(*s, *sc, x0)) return "x_init is not in X_free (bounds, limits or obstacles)";
   *code = PAKR_OK;
@@ -1008,6 +1030,393 @@ void pakr_batch_destroy(pakr_batch* bt) {
   if (bt->cap_stream) (void)hipStreamDestroy(bt->cap_stream);
   if (bt->own_ws && bt->ws) (void)hipFree(bt->ws);
   delete bt;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Trajectory refinement
+// ---------------------------------------------------------------------------
+struct pakr_refiner {
+  DevProblem P;
+  RefineParams R;
+  hipStream_t stream = nullptr;
+  float* obs = nullptr;
+  size_t shmem = 0;
+  std::string err;
+};
+
+namespace {
+
+int rfail(pakr_refiner* r, int code, const std::string& msg) {
+  if (r) r->err = msg;
+  else g_init_error = msg;
+  return code;
+}
+
+std::string validate_refine(const pakr_refine_params* rp, int m) {
+  if (!(rp->w_effort >= 0.0f) || !(rp->w_goal >= 0.0f) || !(rp->w_collision >= 0.0f) ||
+      !finite_f(rp->w_effort) || !finite_f(rp->w_goal) || !finite_f(rp->w_collision))
+    return "refinement weights must be finite and >= 0";
+  if (!(rp->beta > 0.0f) || !finite_f(rp->beta)) return "beta must be finite and > 0";
+  if (!(rp->delta >= 0.0f) || !finite_f(rp->delta)) return "delta must be finite and >= 0";
+  for (int c = 0; c < m; ++c) {
+    if (!finite_f(rp->u_ref[c])) return "u_ref must be finite";
+    if (!(rp->u_scale[c] > 0.0f) || !finite_f(rp->u_scale[c])) return "u_scale must be > 0";
+  }
+  return std::string();
+}
+
+RefineParams to_device(const pakr_refine_params& rp) {
+  RefineParams R;
+  std::memset(&R, 0, sizeof R);
+  R.w_u = rp.w_effort;
+  R.w_g = rp.w_goal;
+  R.w_c = rp.w_collision;
+  R.beta = rp.beta;
+  R.delta = rp.delta;
+  for (int c = 0; c < PAKR_MAX_M; ++c) {
+    R.u_ref[c] = rp.u_ref[c];
+    R.u_scale[c] = rp.u_scale[c] > 0.0f ? rp.u_scale[c] : 1.0f;
+  }
+  return R;
+}
+
+// Largest trajectory count and edge count one call accepts.
+constexpr int MAX_TRAJ = 1 << 20;
+constexpr int MAX_EDGES = 1 << 16;
+
+bool traj_sizes_ok(const pakr_refiner* r, int n, int M) {
+  return r && n >= 1 && n <= MAX_TRAJ && M >= 1 && M <= MAX_EDGES &&
+         (size_t)M * (size_t)r->P.T < (size_t)1 << 30;
+}
+
+size_t ckpt_bytes_of(const pakr_refiner* r, int n, int M) {
+  return sizeof(float) * (size_t)n * ((size_t)M * r->P.T + 1) * (size_t)r->P.d;
+}
+
+template <int SYS>
+const void* traj_kernel(int which) {
+  if (which == 0) return reinterpret_cast<const void*>(&k_rollout_fwd<SYS>);
+  if (which == 1) return reinterpret_cast<const void*>(&k_rollout_bwd<SYS>);
+  return reinterpret_cast<const void*>(&k_check_path<SYS>);
+}
+
+const void* traj_kernel_for(int sys, int which) {
+  switch (sys) {
+    case PAKR_DI2: return traj_kernel<PAKR_DI2>(which);
+    case PAKR_DI3: return traj_kernel<PAKR_DI3>(which);
+    case PAKR_CAR: return traj_kernel<PAKR_CAR>(which);
+    default: return traj_kernel<PAKR_QUAD>(which);
+  }
+}
+
+int launch_traj(pakr_refiner* r, int which, TrajArgs& a) {
+  void* args[] = {&a};
+  hipError_t e = hipLaunchKernel(traj_kernel_for(r->P.system, which), dim3(a.n_traj), dim3(WAVE),
+                                 args, r->shmem, r->stream);
+  if (e != hipSuccess) return rfail(r, PAKR_E_HIP, std::string("launch: ") + hipGetErrorString(e));
+  return PAKR_OK;
+}
+
+int launch_adam(pakr_refiner* r, int n, int M, const float* U, float* U_out, const float* gU,
+                float* m1, float* m2, const float* lr_traj, int step, float lr) {
+  const size_t total = (size_t)n * M * r->P.m;
+  AdamArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.U = U;
+  a.U_out = U_out;
+  a.gU = gU;
+  a.m1 = m1;
+  a.m2 = m2;
+  a.lr_traj = lr_traj;
+  a.n = (int)total;
+  a.m = r->P.m;
+  a.per_traj = M * r->P.m;
+  a.lr = lr;
+  a.b1 = 0.9f;
+  a.b2 = 0.999f;
+  a.eps = 1e-8f;
+  a.c1 = (float)(1.0 - std::pow(0.9, step));
+  a.c2 = (float)(1.0 - std::pow(0.999, step));
+  for (int c = 0; c < PAKR_MAX_M; ++c) {
+    a.u_lo[c] = r->P.u_lo[c];
+    a.u_hi[c] = r->P.u_hi[c];
+  }
+  void* args[] = {&a};
+  const int blocks = (int)((total + 255) / 256);
+  hipError_t e = hipLaunchKernel(reinterpret_cast<const void*>(&k_adam_project), dim3(blocks),
+                                 dim3(256), args, 0, r->stream);
+  if (e != hipSuccess) return rfail(r, PAKR_E_HIP, std::string("launch: ") + hipGetErrorString(e));
+  return PAKR_OK;
+}
+
+int launch_accept(pakr_refiner* r, int n, int M, float* U, const float* Ut, float* J,
+                  const float* Jt, float* lr_traj) {
+  AcceptArgs a;
+  a.U = U;
+  a.U_trial = Ut;
+  a.J = J;
+  a.J_trial = Jt;
+  a.lr_traj = lr_traj;
+  a.per_traj = M * r->P.m;
+  a.n = n * a.per_traj;
+  void* args[] = {&a};
+  hipError_t e = hipLaunchKernel(reinterpret_cast<const void*>(&k_accept),
+                                 dim3((a.n + 255) / 256), dim3(256), args, 0, r->stream);
+  if (e != hipSuccess) return rfail(r, PAKR_E_HIP, std::string("launch: ") + hipGetErrorString(e));
+  return PAKR_OK;
+}
+
+int launch_fill(pakr_refiner* r, float* x, int n, float v) {
+  void* args[] = {&x, &n, &v};
+  hipError_t e = hipLaunchKernel(reinterpret_cast<const void*>(&k_fill), dim3((n + 255) / 256),
+                                 dim3(256), args, 0, r->stream);
+  if (e != hipSuccess) return rfail(r, PAKR_E_HIP, std::string("launch: ") + hipGetErrorString(e));
+  return PAKR_OK;
+}
+
+int launch_copy(pakr_refiner* r, float* dst, const float* src, int n) {
+  hipError_t e = hipMemcpyAsync(dst, src, sizeof(float) * (size_t)n, hipMemcpyDeviceToDevice,
+                                r->stream);
+  if (e != hipSuccess) return rfail(r, PAKR_E_HIP, std::string("copy: ") + hipGetErrorString(e));
+  return PAKR_OK;
+}
+
+struct RefineLayout {
+  size_t ckpt, m1, m2, ut, gu, j, jt, ones, lr, total;
+};
+
+RefineLayout refine_layout(const pakr_refiner* r, int n, int M) {
+  RefineLayout L{};
+  const size_t nv = (size_t)n * M * r->P.m;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  L.ckpt = take(ckpt_bytes_of(r, n, M));
+  L.m1 = take(sizeof(float) * nv);
+  L.m2 = take(sizeof(float) * nv);
+  L.ut = take(sizeof(float) * nv);
+  L.gu = take(sizeof(float) * nv);
+  L.j = take(sizeof(float) * n);
+  L.jt = take(sizeof(float) * n);
+  L.ones = take(sizeof(float) * n);
+  L.lr = take(sizeof(float) * n);
+  L.total = off;
+  return L;
+}
+
+TrajArgs traj_args(const pakr_refiner* r, int n, int M) {
+  TrajArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.P = r->P;
+  a.R = r->R;
+  a.obs = r->obs;
+  a.n_traj = n;
+  a.M = M;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pakr_refiner_init(const pakr_system* sys, const pakr_scene* scene, const pakr_goal* goal,
+                      const pakr_params* params, const pakr_refine_params* refine, void* stream,
+                      pakr_refiner** out) {
+  if (!out) return rfail(nullptr, PAKR_E_INVALID_ARG, "null output pointer");
+  *out = nullptr;
+  if (!sys || !scene || !goal || !params || !refine)
+    return rfail(nullptr, PAKR_E_INVALID_ARG, "null argument");
+  std::string m = validate_system(sys, scene);
+  if (m.empty() && params->T < 1) m = "T must be >= 1";
+  if (m.empty() && (!(params->dt > 0.0f) || !std::isfinite(params->dt)))
+    m = "dt must be finite and > 0";
+  if (m.empty() && params->cost_kind != PAKR_COST_DURATION &&
+      params->cost_kind != PAKR_COST_PATH_LENGTH)
+    m = "bad cost_kind";
+  if (m.empty()) m = validate_scene(scene);
+  if (m.empty()) m = validate_refine(refine, sys->m);
+  if (!m.empty()) return rfail(nullptr, PAKR_E_INVALID_ARG, m);
+  m = validate_goal(goal, scene);
+  if (!m.empty()) return rfail(nullptr, PAKR_E_GOAL_INVALID, m);
+
+  pakr_refiner* r = new (std::nothrow) pakr_refiner();
+  if (!r) return rfail(nullptr, PAKR_E_INVALID_ARG, "out of host memory");
+  r->stream = static_cast<hipStream_t>(stream);
+  // the planner's record of the query; B, A, n_cap do not matter here
+  pakr_params prm = *params;
+  prm.B = 1;
+  prm.A = 1;
+  prm.n_cap = 2;
+  r->P = make_problem(*sys, *scene, *goal, prm, 1, 1);
+  r->R = to_device(*refine);
+  const std::vector<float> obs = pack_obstacles(*scene);
+  r->shmem = sizeof(float) * std::max<size_t>(obs.size(), 1);
+  hipError_t e = hipMalloc(&r->obs, r->shmem);
+  if (e == hipSuccess && !obs.empty())
+    e = hipMemcpyAsync(r->obs, obs.data(), sizeof(float) * obs.size(), hipMemcpyHostToDevice,
+                       r->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
+  if (e != hipSuccess) {
+    int rc = rfail(nullptr, PAKR_E_HIP, std::string("upload obstacles: ") + hipGetErrorString(e));
+    pakr_refiner_destroy(r);
+    return rc;
+  }
+  *out = r;
+  return PAKR_OK;
+}
+
+int pakr_refiner_set_params(pakr_refiner* r, const pakr_refine_params* refine) {
+  if (!r || !refine) return PAKR_E_INVALID_ARG;
+  std::string m = validate_refine(refine, r->P.m);
+  if (!m.empty()) return rfail(r, PAKR_E_INVALID_ARG, m);
+  r->R = to_device(*refine);
+  return PAKR_OK;
+}
+
+size_t pakr_rollout_ckpt_bytes(const pakr_refiner* r, int n, int M) {
+  if (!traj_sizes_ok(r, n, M)) return 0;
+  return ckpt_bytes_of(r, n, M);
+}
+
+int pakr_rollout_fwd(pakr_refiner* r, int n, int M, const float* d_x0, const float* d_U,
+                     void* d_ckpt, size_t ckpt_bytes, float* d_J) {
+  if (!r) return PAKR_E_INVALID_ARG;
+  if (!traj_sizes_ok(r, n, M)) return rfail(r, PAKR_E_INVALID_ARG, "bad trajectory count or M");
+  if (!d_x0 || !d_U || !d_ckpt || !d_J) return rfail(r, PAKR_E_INVALID_ARG, "null device array");
+  if (ckpt_bytes < ckpt_bytes_of(r, n, M))
+    return rfail(r, PAKR_E_WORKSPACE_TOO_SMALL, "checkpoint buffer smaller than required");
+  TrajArgs a = traj_args(r, n, M);
+  a.x0 = d_x0;
+  a.U = d_U;
+  a.ckpt = static_cast<float*>(d_ckpt);
+  a.J = d_J;
+  return launch_traj(r, 0, a);
+}
+
+int pakr_rollout_bwd(pakr_refiner* r, int n, int M, const float* d_U, const void* d_ckpt,
+                     size_t ckpt_bytes, const float* d_gJ, float* d_gU) {
+  if (!r) return PAKR_E_INVALID_ARG;
+  if (!traj_sizes_ok(r, n, M)) return rfail(r, PAKR_E_INVALID_ARG, "bad trajectory count or M");
+  if (!d_U || !d_ckpt || !d_gJ || !d_gU) return rfail(r, PAKR_E_INVALID_ARG, "null device array");
+  if (ckpt_bytes < ckpt_bytes_of(r, n, M))
+    return rfail(r, PAKR_E_WORKSPACE_TOO_SMALL, "checkpoint buffer smaller than required");
+  TrajArgs a = traj_args(r, n, M);
+  a.U = d_U;
+  a.ckpt = const_cast<float*>(static_cast<const float*>(d_ckpt));
+  a.gJ = d_gJ;
+  a.gU = d_gU;
+  return launch_traj(r, 1, a);
+}
+
+int pakr_refine_step(pakr_refiner* r, int n, int M, float* d_U, const float* d_gU, float* d_m1,
+                     float* d_m2, int step, float lr) {
+  if (!r) return PAKR_E_INVALID_ARG;
+  if (!traj_sizes_ok(r, n, M)) return rfail(r, PAKR_E_INVALID_ARG, "bad trajectory count or M");
+  if (!d_U || !d_gU || !d_m1 || !d_m2) return rfail(r, PAKR_E_INVALID_ARG, "null device array");
+  if (step < 1) return rfail(r, PAKR_E_INVALID_ARG, "step counts from 1");
+  if (!(lr > 0.0f) || !std::isfinite(lr)) return rfail(r, PAKR_E_INVALID_ARG, "lr must be > 0");
+  if ((size_t)n * M * r->P.m > (size_t)INT32_MAX)
+    return rfail(r, PAKR_E_INVALID_ARG, "too many control values");
+  return launch_adam(r, n, M, d_U, d_U, d_gU, d_m1, d_m2, nullptr, step, lr);
+}
+
+size_t pakr_refine_workspace_size(const pakr_refiner* r, int n, int M) {
+  if (!traj_sizes_ok(r, n, M) || (size_t)n * M * r->P.m > (size_t)INT32_MAX) return 0;
+  return refine_layout(r, n, M).total;
+}
+
+int pakr_refine_paths(pakr_refiner* r, int n, int M, const float* d_x0, float* d_U, int steps,
+                      float lr, void* d_ws, size_t ws_bytes, float* d_J_before, float* d_J_after) {
+  if (!r) return PAKR_E_INVALID_ARG;
+  if (!traj_sizes_ok(r, n, M) || (size_t)n * M * r->P.m > (size_t)INT32_MAX)
+    return rfail(r, PAKR_E_INVALID_ARG, "bad trajectory count or M");
+  if (!d_x0 || !d_U || !d_ws) return rfail(r, PAKR_E_INVALID_ARG, "null device array");
+  if (steps < 0) return rfail(r, PAKR_E_INVALID_ARG, "steps must be >= 0");
+  if (!(lr > 0.0f) || !std::isfinite(lr)) return rfail(r, PAKR_E_INVALID_ARG, "lr must be > 0");
+  const RefineLayout L = refine_layout(r, n, M);
+  if (ws_bytes < L.total)
+    return rfail(r, PAKR_E_WORKSPACE_TOO_SMALL, "workspace smaller than required");
+  if ((reinterpret_cast<uintptr_t>(d_ws) & 255) != 0)
+    return rfail(r, PAKR_E_INVALID_ARG, "workspace must be 256-byte aligned");
+  char* base = static_cast<char*>(d_ws);
+  float* ckpt = reinterpret_cast<float*>(base + L.ckpt);
+  float* m1 = reinterpret_cast<float*>(base + L.m1);
+  float* m2 = reinterpret_cast<float*>(base + L.m2);
+  float* Ut = reinterpret_cast<float*>(base + L.ut);
+  float* gU = reinterpret_cast<float*>(base + L.gu);
+  float* J = reinterpret_cast<float*>(base + L.j);
+  float* Jt = reinterpret_cast<float*>(base + L.jt);
+  float* ones = reinterpret_cast<float*>(base + L.ones);
+  float* lr_traj = reinterpret_cast<float*>(base + L.lr);
+  const int nv = n * M * r->P.m;
+  // fills by kernel (no memset nodes, so the sequence can be graph-captured)
+  int rc = launch_fill(r, m1, nv, 0.0f);
+  if (rc == PAKR_OK) rc = launch_fill(r, m2, nv, 0.0f);
+  if (rc == PAKR_OK) rc = launch_fill(r, ones, n, 1.0f);
+  if (rc == PAKR_OK) rc = launch_fill(r, lr_traj, n, 1.0f);
+  TrajArgs f = traj_args(r, n, M);
+  f.x0 = d_x0;
+  f.ckpt = ckpt;
+  TrajArgs b = traj_args(r, n, M);
+  b.U = d_U;
+  b.ckpt = ckpt;
+  b.gJ = ones;
+  b.gU = gU;
+  // J of the starting controls
+  f.U = d_U;
+  f.J = J;
+  if (rc == PAKR_OK) rc = launch_traj(r, 0, f);
+  if (rc == PAKR_OK && d_J_before)
+    rc = launch_copy(r, d_J_before, J, n);
+  for (int k = 1; k <= steps && rc == PAKR_OK; ++k) {
+    // checkpoints of the current controls, then the adjoint from them
+    if (k > 1) {
+      f.U = d_U;
+      f.J = Jt;  // J of the current controls is already in J
+      rc = launch_traj(r, 0, f);
+    }
+    if (rc == PAKR_OK) rc = launch_traj(r, 1, b);
+    if (rc == PAKR_OK) rc = launch_adam(r, n, M, d_U, Ut, gU, m1, m2, lr_traj, k, lr);
+    if (rc == PAKR_OK) {
+      f.U = Ut;
+      f.J = Jt;
+      rc = launch_traj(r, 0, f);
+    }
+    if (rc == PAKR_OK) rc = launch_accept(r, n, M, d_U, Ut, J, Jt, lr_traj);
+  }
+  if (rc == PAKR_OK && d_J_after) rc = launch_copy(r, d_J_after, J, n);
+  return rc;
+}
+
+int pakr_check_path(pakr_refiner* r, int n, int M, const float* d_x0, const float* d_U,
+                    int* d_ok, float* d_cost) {
+  if (!r) return PAKR_E_INVALID_ARG;
+  if (!traj_sizes_ok(r, n, M)) return rfail(r, PAKR_E_INVALID_ARG, "bad trajectory count or M");
+  if (!d_x0 || !d_U || !d_ok || !d_cost) return rfail(r, PAKR_E_INVALID_ARG, "null device array");
+  TrajArgs a = traj_args(r, n, M);
+  a.x0 = d_x0;
+  a.U = d_U;
+  a.ok = d_ok;
+  a.cost = d_cost;
+  return launch_traj(r, 2, a);
+}
+
+const char* pakr_refiner_last_error(const pakr_refiner* r) {
+  return r ? r->err.c_str() : g_init_error.c_str();
+}
+
+void pakr_refiner_destroy(pakr_refiner* r) {
+  if (!r) return;
+  if (r->obs) {
+    (void)hipStreamSynchronize(r->stream);
+    (void)hipFree(r->obs);
+  }
+  delete r;
 }
 
 }  // extern "C"

@@ -39,7 +39,11 @@ EXPORTED = ["pakr_workspace_size", "pakr_plan_init", "pakr_plan_destroy", "pakr_
             "pakr_batch_workspace_size", "pakr_batch_init", "pakr_batch_replan",
             "pakr_batch_graph_capture", "pakr_batch_graph_launch", "pakr_batch_status",
             "pakr_batch_solutions", "pakr_batch_extract_path", "pakr_batch_grid",
-            "pakr_batch_last_error", "pakr_batch_destroy"]
+            "pakr_batch_last_error", "pakr_batch_destroy",
+            "pakr_refiner_init", "pakr_refiner_set_params", "pakr_rollout_ckpt_bytes",
+            "pakr_rollout_fwd", "pakr_rollout_bwd", "pakr_refine_step", "pakr_check_path",
+            "pakr_refine_workspace_size", "pakr_refine_paths",
+            "pakr_refiner_last_error", "pakr_refiner_destroy"]
 
 
 class PakrError(RuntimeError):
@@ -91,6 +95,12 @@ class Stats(C.Structure):
 class Solution(C.Structure):
     _fields_ = [("round", C.c_int), ("iter", C.c_int), ("node", C.c_int), ("n_nodes", C.c_int),
                 ("total_iter", C.c_longlong), ("cost", C.c_double), ("t_ms", C.c_double)]
+
+
+class RefineParams(C.Structure):
+    _fields_ = [("w_effort", C.c_float), ("w_goal", C.c_float), ("w_collision", C.c_float),
+                ("beta", C.c_float), ("delta", C.c_float), ("u_ref", C.c_float * MAX_M),
+                ("u_scale", C.c_float * MAX_M)]
 
 
 _lib = None
@@ -162,6 +172,31 @@ def load():
         L.pakr_batch_last_error.restype = C.c_char_p
         L.pakr_batch_destroy.argtypes = [vp]
         L.pakr_batch_destroy.restype = None
+        L.pakr_refiner_init.argtypes = [C.POINTER(System), C.POINTER(Scene), C.POINTER(Goal),
+                                        C.POINTER(Params), C.POINTER(RefineParams), vp,
+                                        C.POINTER(vp)]
+        L.pakr_refiner_init.restype = C.c_int
+        L.pakr_refiner_set_params.argtypes = [vp, C.POINTER(RefineParams)]
+        L.pakr_refiner_set_params.restype = C.c_int
+        L.pakr_rollout_ckpt_bytes.argtypes = [vp, C.c_int, C.c_int]
+        L.pakr_rollout_ckpt_bytes.restype = sz
+        L.pakr_rollout_fwd.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, sz, vp]
+        L.pakr_rollout_fwd.restype = C.c_int
+        L.pakr_rollout_bwd.argtypes = [vp, C.c_int, C.c_int, vp, vp, sz, vp, vp]
+        L.pakr_rollout_bwd.restype = C.c_int
+        L.pakr_refine_step.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, vp, C.c_int, C.c_float]
+        L.pakr_refine_step.restype = C.c_int
+        L.pakr_refine_workspace_size.argtypes = [vp, C.c_int, C.c_int]
+        L.pakr_refine_workspace_size.restype = sz
+        L.pakr_refine_paths.argtypes = [vp, C.c_int, C.c_int, vp, vp, C.c_int, C.c_float, vp, sz,
+                                        vp, vp]
+        L.pakr_refine_paths.restype = C.c_int
+        L.pakr_check_path.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, vp]
+        L.pakr_check_path.restype = C.c_int
+        L.pakr_refiner_last_error.argtypes = [vp]
+        L.pakr_refiner_last_error.restype = C.c_char_p
+        L.pakr_refiner_destroy.argtypes = [vp]
+        L.pakr_refiner_destroy.restype = None
         _lib = L
     return _lib
 

@@ -43,8 +43,10 @@ _PROBE = r"""
 #define P(T, f) printf(#T "." #f " %zu\n", offsetof(T, f))
 int main(void) {
   printf("pakr_system %zu\npakr_scene %zu\npakr_goal %zu\npakr_params %zu\n"
-         "pakr_stats %zu\npakr_solution %zu\n", sizeof(pakr_system), sizeof(pakr_scene),
-         sizeof(pakr_goal), sizeof(pakr_params), sizeof(pakr_stats), sizeof(pakr_solution));
+         "pakr_stats %zu\npakr_solution %zu\npakr_refine_params %zu\n", sizeof(pakr_system),
+         sizeof(pakr_scene), sizeof(pakr_goal), sizeof(pakr_params), sizeof(pakr_stats),
+         sizeof(pakr_solution), sizeof(pakr_refine_params));
+  P(pakr_refine_params, delta); P(pakr_refine_params, u_ref); P(pakr_refine_params, u_scale);
   P(pakr_system, vnorm_max); P(pakr_scene, sph_r); P(pakr_params, cost_bound);
   P(pakr_params, seed); P(pakr_params, max_path_edges); P(pakr_params, lanes_per_candidate); P(pakr_params, workgroups_per_cu); P(pakr_stats, c_best);
   P(pakr_stats, call_iters); P(pakr_stats, insert_ms); P(pakr_stats, step_ms); P(pakr_stats, clock_end_ms); P(pakr_solution, t_ms);
@@ -62,7 +64,8 @@ def test_struct_layouts_match_header(tmp_path):
     out = dict(line.rsplit(" ", 1) for line in subprocess.check_output([str(exe)], text=True)
                .strip().splitlines())
     sizes = {"pakr_system": pakr.System, "pakr_scene": pakr.Scene, "pakr_goal": pakr.Goal,
-             "pakr_params": pakr.Params, "pakr_stats": pakr.Stats, "pakr_solution": pakr.Solution}
+             "pakr_params": pakr.Params, "pakr_stats": pakr.Stats, "pakr_solution": pakr.Solution,
+             "pakr_refine_params": pakr.RefineParams}
     for name, cls in sizes.items():
         assert int(out[name]) == C.sizeof(cls), name
     for key, val in out.items():
@@ -157,3 +160,32 @@ def test_batch_workspace_size_covers_every_query():
     total = pakr.batch_workspace_size(pakr.CBatch(probs))
     single = sum(4 * p.n_cap * (p.d + p.m + 2) for p in probs)
     assert total >= single
+
+
+def _refiner_code(prob, rs):
+    from paper_2607_03987_amd import refine
+    q = pakr.CQuery(prob)
+    rp = refine.c_refine_params(rs)
+    h = C.c_void_p()
+    rc = pakr.load().pakr_refiner_init(C.byref(q.system), C.byref(q.scene), C.byref(q.goal),
+                                       C.byref(q.params), C.byref(rp), None, C.byref(h))
+    assert rc != 0 and not h.value  # every case here fails validation before any device call
+    return rc, pakr.load().pakr_refiner_last_error(None).decode()
+
+
+@pytest.mark.parametrize("mutate,rs_over,code,msg", [
+    (lambda p: p, dict(beta=0.0), -1, "beta"),
+    (lambda p: p, dict(beta=float("inf")), -1, "beta"),
+    (lambda p: p, dict(delta=-0.1), -1, "delta"),
+    (lambda p: p, dict(w_c=-1.0), -1, "weights"),
+    (lambda p: p, dict(u_scale=(1.0, 0.0)), -1, "u_scale"),
+    (lambda p: p, dict(u_ref=(float("nan"), 0.0)), -1, "u_ref"),
+    (lambda p: p.replace(T=0), {}, -1, "T"),
+    (lambda p: p.replace(dt=np.float32(-1)), {}, -1, "dt"),
+    (lambda p: p.replace(cost_kind=5), {}, -1, "cost_kind"),
+    (lambda p: p.replace(goal_r=np.float32(0)), {}, -3, "goal"),
+])
+def test_refiner_init_rejects_malformed_arguments(mutate, rs_over, code, msg):
+    p = mutate(W.config_c1())
+    rc, err = _refiner_code(p, W.refine_settings(W.config_c1(), **rs_over))
+    assert rc == code and msg in err, (rc, err)

@@ -1,0 +1,276 @@
+"""GPU parity of the trajectory refinement (hand-written RK4 adjoint).
+
+The float32 rollout, its adjoint and the planner's hard path check run in
+libpakr kernels and are compared with the FP64 oracle:
+  - J and the checkpointed states against the oracle's objective and rollout;
+  - dJ/dU against the oracle's complex-step gradient (relative L2 error and
+    cosine), on every system, several trajectories per launch, edge cases
+    (one edge, one step, many trajectories);
+  - the torch.autograd.Function gives the adjoint's gradient;
+  - the hard check agrees with the oracle's edge validity and goal test;
+  - refining a path the planner found on the quadrotor lowers J, and an
+    accepted refined path passes the oracle's own validity check.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2607_03987_amd import pakr, refine, workloads as W
+from tests.parity import rel_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def rp_of(rs):
+    return oracle.refine_params(rs.w_u, rs.w_g, rs.w_c, rs.beta, rs.delta, rs.u_ref, rs.u_scale)
+
+
+def controls(prob, n, M, rng, spread=1.0):
+    lo = np.asarray(prob.u_lo, np.float64)[:prob.m]
+    hi = np.asarray(prob.u_hi, np.float64)[:prob.m]
+    mid, half = 0.5 * (lo + hi), 0.5 * (hi - lo)
+    return (mid + spread * half * rng.uniform(-1, 1, (n, M, prob.m))).astype(np.float32)
+
+
+def starts(prob, n, rng):
+    x = np.repeat(np.asarray(prob.x_init, np.float32)[None, :], n, 0)
+    x[:, :prob.npos] += rng.uniform(-0.3, 0.3, (n, prob.npos)).astype(np.float32)
+    return x
+
+
+# The car's steering angle integrates the steering rate with no limit in f;
+# controls are kept small enough that |phi| stays below 1 rad, away from the
+# pole of tan(phi) where FP32 and FP64 trajectories part.
+CASES = [("c1", 10, 6, 1.0), ("c2", 20, 5, 1.0), ("c3", 25, 5, 0.35), ("c4", 40, 4, 0.25)]
+
+
+@pytest.mark.parametrize("cfg,T,M,spread", CASES)
+def test_forward_and_adjoint_match_oracle(cfg, T, M, spread):
+    prob = W.CONFIGS[cfg]().replace(T=T)
+    print(f"case refine {cfg} T {T} M {M}", flush=True)
+    rs = W.refine_settings(prob)
+    rp = rp_of(rs)
+    cp = oracle.CProblem(prob)
+    ref = refine.Refiner(prob, rs)
+    rng = np.random.default_rng(7)
+    n = 6
+    U = controls(prob, n, M, rng, spread)
+    x0 = starts(prob, n, rng)
+    Ud, x0d = torch.from_numpy(U).cuda(), torch.from_numpy(x0).cuda()
+    J, ckpt = ref.forward(x0d, Ud)
+    gU = ref.backward(Ud, ckpt, torch.ones(n, device="cuda"))
+    J, ckpt, gU = J.cpu().numpy(), ckpt.cpu().numpy(), gU.cpu().numpy()
+    for p in range(n):
+        Jo = oracle.traj_cost(cp, rp, x0[p].astype(np.float64), U[p].astype(np.float64))
+        assert abs(J[p] - Jo) <= 2e-4 * max(abs(Jo), 1.0), (p, J[p], Jo)
+        # checkpoints: the oracle's rollout edge by edge from the same start
+        x = x0[p].astype(np.float64)
+        states = [x]
+        for e in range(M):
+            traj = oracle.rollout(cp, states[-1], U[p, e].astype(np.float64), T, float(prob.dt))
+            states.extend(traj[1:])
+        states = np.array(states)
+        if prob.system == W.CAR:
+            assert np.abs(states[:, 4]).max() < 1.0
+        assert rel_err(ckpt[p], states).max() <= 1e-3, p
+        go = oracle.traj_grad(cp, rp, x0[p].astype(np.float64), U[p].astype(np.float64))
+        err = np.linalg.norm(gU[p] - go) / max(np.linalg.norm(go), 1e-12)
+        cos = float((gU[p] * go).sum() / (np.linalg.norm(gU[p]) * np.linalg.norm(go) + 1e-30))
+        print(f"  traj {p}: J {J[p]:.6g} oracle {Jo:.6g}; grad rel L2 {err:.2e} cos {cos:.8f}",
+              flush=True)
+        assert err <= 2e-3 and cos >= 0.99999, (p, err, cos)
+    ref.close()
+
+
+@pytest.mark.parametrize("T,M", [(1, 1), (3, 1), (1, 7)])
+def test_adjoint_edge_sizes(T, M):
+    prob = W.config_c4().replace(T=T)
+    rs = W.refine_settings(prob)
+    rp, cp = rp_of(rs), oracle.CProblem(prob)
+    ref = refine.Refiner(prob, rs)
+    rng = np.random.default_rng(T * 10 + M)
+    U = controls(prob, 3, M, rng, 0.5)
+    x0 = starts(prob, 3, rng)
+    Ud, x0d = torch.from_numpy(U).cuda(), torch.from_numpy(x0).cuda()
+    J, ckpt = ref.forward(x0d, Ud)
+    assert ckpt.shape == (3, M * T + 1, prob.d)
+    gJ = torch.tensor([1.0, -2.0, 0.5], device="cuda")
+    gU = ref.backward(Ud, ckpt, gJ).cpu().numpy()
+    for p in range(3):
+        go = float(gJ[p]) * oracle.traj_grad(cp, rp, x0[p].astype(np.float64),
+                                             U[p].astype(np.float64))
+        assert np.linalg.norm(gU[p] - go) <= 1e-3 * np.linalg.norm(go), p
+    ref.close()
+
+
+def test_many_trajectories_sampled():
+    prob = W.config_c2()
+    rs = W.refine_settings(prob)
+    rp, cp = rp_of(rs), oracle.CProblem(prob)
+    ref = refine.Refiner(prob, rs)
+    rng = np.random.default_rng(99)
+    n, M = 2048, 8
+    U = controls(prob, n, M, rng)
+    x0 = starts(prob, n, rng)
+    Ud, x0d = torch.from_numpy(U).cuda(), torch.from_numpy(x0).cuda()
+    J, ckpt = ref.forward(x0d, Ud)
+    gU = ref.backward(Ud, ckpt, torch.ones(n, device="cuda"))
+    J, gU = J.cpu().numpy(), gU.cpu().numpy()
+    for p in rng.choice(n, 12, replace=False):
+        Jo = oracle.traj_cost(cp, rp, x0[p].astype(np.float64), U[p].astype(np.float64))
+        go = oracle.traj_grad(cp, rp, x0[p].astype(np.float64), U[p].astype(np.float64))
+        assert abs(J[p] - Jo) <= 2e-4 * max(abs(Jo), 1.0)
+        assert np.linalg.norm(gU[p] - go) <= 2e-3 * np.linalg.norm(go)
+    ref.close()
+
+
+def test_autograd_function_gives_adjoint():
+    prob = W.config_c3()
+    ref = refine.Refiner(prob)
+    rng = np.random.default_rng(4)
+    U = torch.from_numpy(controls(prob, 4, 5, rng)).cuda().requires_grad_(True)
+    x0 = torch.from_numpy(starts(prob, 4, rng)).cuda()
+    w = torch.tensor([1.0, 0.5, -1.0, 2.0], device="cuda")
+    J = refine.rollout_cost(ref, x0, U)
+    (J * w).sum().backward()
+    J2, ckpt = ref.forward(x0, U.detach())
+    gU = ref.backward(U.detach(), ckpt, w)
+    assert torch.equal(J.detach(), J2)
+    assert torch.allclose(U.grad, gU, rtol=0, atol=0)
+    ref.close()
+
+
+def _oracle_path_ok(cp, prob, x0, U):
+    """The oracle's edge test along the path: (all valid, any ambiguous, final state, cost)."""
+    x, ok, amb_any, cost = x0.astype(np.float64), True, False, 0.0
+    for e in range(U.shape[0]):
+        v, xT, cost, amb = oracle.edge(cp, x, cost, U[e].astype(np.float64))
+        ok, amb_any = ok and v, amb_any or bool(amb)
+        x = xT
+    return ok, amb_any, x, cost
+
+
+@pytest.mark.parametrize("cfg", ["c1", "c3"])   # path-length cost, duration cost
+def test_check_path_matches_oracle(cfg):
+    prob = W.CONFIGS[cfg]()
+    cp = oracle.CProblem(prob)
+    ref = refine.Refiner(prob)
+    rng = np.random.default_rng(12)
+    n, M = 64, 6
+    U = controls(prob, n, M, rng, 0.35 if cfg == "c3" else 1.0)
+    x0 = starts(prob, n, rng)
+    ok, cost = ref.check(torch.from_numpy(x0).cuda(), torch.from_numpy(U).cuda())
+    ok, cost = ok.cpu().numpy(), cost.cpu().numpy()
+    n_valid = 0
+    goal = np.asarray(prob.goal_c, np.float64)
+    for p in range(n):
+        v, amb, xN, co = _oracle_path_ok(cp, prob, x0[p], U[p])
+        if not amb:
+            assert bool(ok[p] & 1) == v, p
+        n_valid += int(v)
+        dist = np.linalg.norm(xN[:prob.npos] - goal)
+        assert bool(ok[p] & 2) == (dist <= float(prob.goal_r)) or abs(dist - prob.goal_r) < 1e-4
+        assert cost[p] == pytest.approx(co, rel=1e-4), p
+    assert 0 < n_valid < n  # both outcomes are exercised
+
+
+def test_check_path_goal_bit():
+    """A straight double-integrator path that ends in the goal ball sets bit 1."""
+    prob = W.config_c1().replace(box_c=np.zeros((0, 2), np.float32),
+                                 box_h=np.zeros((0, 2), np.float32))
+    ref = refine.Refiner(prob)
+    # along the diagonal: 2 edges at +1, 14 cruising at speed 1 per axis, 2 at -1
+    U = np.array([[1, 1]] * 2 + [[0, 0]] * 14 + [[-1, -1]] * 2, np.float32)[None]
+    x0 = np.float32([[1.0, 1.0, 0.0, 0.0]])
+    ok, cost = ref.check(torch.from_numpy(x0).cuda(), torch.from_numpy(U).cuda())
+    v, amb, xN, co = _oracle_path_ok(oracle.CProblem(prob), prob, x0[0], U[0])
+    assert v and not amb
+    assert np.linalg.norm(xN[:2] - np.asarray(prob.goal_c)) < 1e-6
+    assert int(ok[0]) == 3
+    U[0, -1] = 0.0   # one braking edge short: ends 0.125 past the centre per axis, inside
+    ok, _ = ref.check(torch.from_numpy(x0).cuda(), torch.from_numpy(U).cuda())
+    assert int(ok[0]) == 3
+    U[0, -2:] = 0.0  # no braking: ends 0.5 past the centre per axis, outside the ball
+    ok, _ = ref.check(torch.from_numpy(x0).cuda(), torch.from_numpy(U).cuda())
+    assert int(ok[0]) == 1
+
+
+def test_refine_planner_path_on_quadrotor():
+    prob = W.config_c4()
+    print("case refine c4: plan 300 ms then 50 adjoint steps", flush=True)
+    plan = pakr.Plan(prob)
+    plan.replan(budget_ms=300.0)
+    st = plan.status()
+    if st["n_solutions"] == 0:
+        plan.close()
+        pytest.skip("no solution within the budget")
+    states, actions, cost = plan.extract_path()
+    c_best = st["c_best"]
+    plan.close()
+    M = actions.shape[0]
+    ref = refine.Refiner(prob)
+    x0 = torch.from_numpy(states[:1].astype(np.float32)).cuda()
+    U = torch.from_numpy(actions[None].astype(np.float32)).cuda()
+    ok0, cost0 = ref.check(x0, U)
+    assert int(ok0[0]) == 3, "the planner's own path must pass its check"
+    assert float(cost0[0]) == pytest.approx(cost, rel=1e-5)
+    res = refine.refine_path(ref, x0, U, cost_bound=c_best)
+    J0, J1 = float(res["J_before"][0]), float(res["J_after"][0])
+    print(f"  M {M}: J {J0:.5g} -> {J1:.5g}, ok {int(res['ok'][0])}, "
+          f"accepted {bool(res['accepted'][0])}", flush=True)
+    assert J1 <= J0
+    Uo = res["U_out"][0].cpu().numpy()
+    lo, hi = np.asarray(prob.u_lo)[:prob.m], np.asarray(prob.u_hi)[:prob.m]
+    assert np.all(Uo >= lo) and np.all(Uo <= hi)
+    if bool(res["accepted"][0]):
+        v, amb, xN, _ = _oracle_path_ok(oracle.CProblem(prob), prob, states[0], Uo)
+        assert v or amb
+    ref.close()
+
+
+def test_refine_never_raises_j_and_keeps_controls_in_the_box():
+    prob = W.config_c2()
+    rs = W.refine_settings(prob)
+    rp, cp = rp_of(rs), oracle.CProblem(prob)
+    ref = refine.Refiner(prob, rs)
+    rng = np.random.default_rng(21)
+    n, M = 16, 6
+    U = torch.from_numpy(controls(prob, n, M, rng, 0.5)).cuda()
+    x0 = torch.from_numpy(starts(prob, n, rng)).cuda()
+    res = refine.refine_path(ref, x0, U, steps=30)
+    J0, J1 = res["J_before"].cpu().numpy(), res["J_after"].cpu().numpy()
+    assert np.all(J1 <= J0) and np.mean(J1 < 0.9 * J0) > 0.5
+    Ur = res["U_refined"].cpu().numpy()
+    assert np.all(Ur >= -1.0) and np.all(Ur <= 1.0)
+    # J_after is the objective of the returned controls (oracle, FP64)
+    for p in range(0, n, 5):
+        Jo = oracle.traj_cost(cp, rp, x0[p].cpu().numpy().astype(np.float64),
+                              Ur[p].astype(np.float64))
+        assert abs(J1[p] - Jo) <= 2e-4 * max(abs(Jo), 1.0)
+    # zero steps leave the controls alone
+    res0 = refine.refine_path(ref, x0, U, steps=0)
+    assert torch.equal(res0["U_refined"], U)
+    assert torch.equal(res0["J_before"], res0["J_after"])
+    ref.close()
+
+
+def test_refiner_rejects_bad_arguments():
+    prob = W.config_c1()
+    with pytest.raises(pakr.PakrError):
+        refine.Refiner(prob, W.refine_settings(prob, beta=0.0))
+    with pytest.raises(pakr.PakrError):
+        refine.Refiner(prob, W.refine_settings(prob, u_scale=(0.0, 1.0)))
+    ref = refine.Refiner(prob)
+    U = torch.zeros((2, 3, prob.m), device="cuda")
+    x0 = torch.zeros((2, prob.d), device="cuda")
+    J, ckpt = ref.forward(x0, U)
+    small = ckpt.reshape(-1)[:10]
+    rc = pakr.load().pakr_rollout_bwd(ref.h, 2, 3, U.data_ptr(), small.data_ptr(), 40,
+                                      J.data_ptr(), U.data_ptr())
+    assert rc == -4
+    assert pakr.load().pakr_rollout_ckpt_bytes(ref.h, 0, 3) == 0
+    ref.close()
