@@ -9,7 +9,9 @@ created (inputs resident in HBM) before the timed region.
 
 Printed: one JSON line with expansions/s over the timed steps, time to first
 and to converged solution, the roofline of the planner kernel and the FP64
-reference's throughput on this host's CPU.
+reference's throughput on this host's CPU; then, outside the timed steps, the
+batched multi-query form against the plain per-query form, and the adjoint
+refinement of a quadrotor path.
 """
 import argparse
 import itertools
@@ -158,6 +160,68 @@ def batched_vs_plain(torch, pakr, W, n_queries, rounds, iters_per_round, lanes=1
     }
 
 
+def refinement_leg(torch, pakr, refine, W, budget_ms, n_multi):
+    """Quadrotor workload: AO-x for `budget_ms`, then the adjoint refinement of
+    the best path's controls (50 safeguarded Adam steps, each one forward and
+    one adjoint rollout plus a trial rollout), and the planner's hard check.
+    Also the throughput of the same refinement on n_multi paths at once
+    (the found path with seeded control perturbations of 0.2% of the box)."""
+    import numpy as np
+    prob = W.config_c4(seed=0)
+    plan = pakr.Plan(prob)
+    plan.replan(budget_ms=budget_ms)
+    st = plan.status()
+    out = {"workload": "12D quadrotor AO-x, [0,10]^3, 50 spheres r U(0.3,1.2), B 8192, A 16, "
+                       f"T 40, dt 0.02, tree capacity 2^20, {budget_ms:.0f} ms, then 50 adjoint "
+                       "steps on the best path",
+           "solved": st["n_solutions"] > 0, "c_best": st["c_best"]}
+    if st["n_solutions"] == 0:
+        plan.close()
+        return out
+    states, actions, cost = plan.extract_path()
+    plan.close()
+    rs = W.refine_settings(prob)
+    ref = refine.Refiner(prob, rs)
+    stream = torch.cuda.current_stream()
+    M = actions.shape[0]
+    x0 = torch.from_numpy(states[:1].astype(np.float32)).cuda()
+    U = torch.from_numpy(actions[None].astype(np.float32)).cuda()
+    refine.refine_path(ref, x0, U, steps=2)  # warm-up
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    res = refine.refine_path(ref, x0, U, steps=rs.steps, cost_bound=st["c_best"])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    rng = np.random.default_rng(0)
+    half = 0.5 * (np.asarray(prob.u_hi) - np.asarray(prob.u_lo))[:prob.m]
+    Um = np.repeat(actions[None], n_multi, 0) + 0.002 * half * rng.uniform(-1, 1, (n_multi, M,
+                                                                                  prob.m))
+    Um = np.clip(Um, np.asarray(prob.u_lo)[:prob.m], np.asarray(prob.u_hi)[:prob.m])
+    Um = torch.from_numpy(Um.astype(np.float32)).cuda()
+    xm = x0.repeat(n_multi, 1)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    resm = refine.refine_path(ref, xm, Um, steps=rs.steps, cost_bound=st["c_best"])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_multi = e0.elapsed_time(e1)
+    ref.close()
+    out.update({
+        "edges": M, "rk4_steps_per_rollout": M * prob.T,
+        "J_before": float(res["J_before"][0]), "J_after": float(res["J_after"][0]),
+        "check_ok_bits": int(res["ok"][0]), "accepted": bool(res["accepted"][0]),
+        "refine_ms": ms, "ms_per_adjoint_step": ms / rs.steps,
+        "multi": {"paths": n_multi, "refine_ms": ms_multi,
+                  "path_steps_per_s": n_multi * rs.steps / (ms_multi / 1e3),
+                  "accepted": int(resm["accepted"].sum()),
+                  "J_reduction_median": float((1 - resm["J_after"] / resm["J_before"])
+                                              .median())},
+    })
+    return out
+
+
 def cpu_baseline(prob, seconds):
     """Time the FP64 reference (single thread) on the same query for ~`seconds`."""
     import oracle
@@ -190,6 +254,9 @@ def main():
     ap.add_argument("--batch-rounds", type=int, default=2)
     ap.add_argument("--batch-iters-per-round", type=int, default=50)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-refine", action="store_true")
+    ap.add_argument("--refine-budget-ms", type=float, default=500.0)
+    ap.add_argument("--refine-paths", type=int, default=256)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before timing, run one plain device copy of this size (a known-size "
                          "kernel against which HBM counters are scaled)")
@@ -201,7 +268,7 @@ def main():
 
     import torch
 
-    from paper_2607_03987_amd import _build, autotune, pakr, workloads as W
+    from paper_2607_03987_amd import _build, autotune, pakr, refine, workloads as W
 
     if not os.path.exists(pakr.LIB_PATH):
         _build.build(force=True)
@@ -309,6 +376,7 @@ def main():
                      "kernel": "k_plan<DI3> (persistent AO-x planner), one launch per query"},
         "cpu_baseline": None,
         "batched": None,
+        "refinement": None,
     }
     for p in plans:
         p.close()
@@ -317,6 +385,9 @@ def main():
                                           args.batch_iters_per_round,
                                           lanes=autotune.batch_lanes(tuned),
                                           settings=autotune.batch_settings(tuned))
+    if not args.no_refine:
+        out["refinement"] = refinement_leg(torch, pakr, refine, W, args.refine_budget_ms,
+                                           args.refine_paths)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W.config_c2(seed=0), args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -479,6 +479,7 @@ struct pakr_batch {
   void* ws = nullptr;
   bool own_ws = false;
   std::vector<KArgs> args;
+  std::vector<int> order;  // device queue position -> query (longest estimated work first)
   KArgs* d_args = nullptr;
   int* d_queue = nullptr;
   size_t shmem = 0;
@@ -786,6 +787,17 @@ const char* pakr_error_string(int code) {
 
 namespace {
 
+// Relative work of one iteration of a query: the rollout arithmetic of its B
+// candidates plus the nearest-neighbour scan of K targets over a tree taken
+// as half of what one round can grow (a scheduling estimate only).
+double query_work(const DevProblem& Q) {
+  const double f_eval = Q.system == PAKR_QUAD ? 84.0 : (Q.system == PAKR_CAR ? 8.0 : 0.0);
+  const double roll =
+      (double)Q.B * Q.T * (12.0 * Q.d + 4.0 * f_eval + 3.0 * Q.npos * (Q.n_box + Q.n_sph));
+  const double tree = 0.5 * std::min((double)Q.n_cap, (double)Q.B * Q.max_iters_per_round);
+  return roll + (double)Q.K * tree * 3.0 * Q.d;
+}
+
 int batch_lanes(const pakr_params& p) { return p.lanes_per_candidate > 0 ? p.lanes_per_candidate : 1; }
 
 // Offsets of the batch workspace: queue word, argument table, then one
@@ -891,6 +903,14 @@ int pakr_batch_init(int n, const pakr_system* sys, const pakr_scene* scenes,
       return rc;
     }
   }
+  // Longest-processing-time-first: the queue hands out the queries with the
+  // most estimated work per round first, so the long ones do not start last.
+  std::vector<double> work((size_t)n);
+  for (int q = 0; q < n; ++q) work[q] = query_work(bt->args[q].P);
+  bt->order.resize((size_t)n);
+  for (int q = 0; q < n; ++q) bt->order[q] = q;
+  std::stable_sort(bt->order.begin(), bt->order.end(),
+                   [&](int a, int b) { return work[a] > work[b]; });
   *out = bt;
   return PAKR_OK;
 }
@@ -902,7 +922,9 @@ int batch_enqueue(pakr_batch* bt, double budget_ms, int max_rounds, long long ma
                   hipStream_t s, bool upload) {
   if (upload) {
     for (auto& a : bt->args) set_limits(a, max_iters, max_rounds, budget_ms, bt->ticks_per_ms);
-    hipError_t e = hipMemcpyAsync(bt->d_args, bt->args.data(), sizeof(KArgs) * bt->args.size(),
+    std::vector<KArgs> table(bt->args.size());
+    for (size_t i = 0; i < table.size(); ++i) table[i] = bt->args[(size_t)bt->order[i]];
+    hipError_t e = hipMemcpyAsync(bt->d_args, table.data(), sizeof(KArgs) * table.size(),
                                   hipMemcpyHostToDevice, bt->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(bt->stream);  // pageable source
     if (e != hipSuccess) return bhip_fail(bt, e, "upload batch arguments");
