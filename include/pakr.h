@@ -259,10 +259,12 @@ const char* pakr_last_error(const pakr_plan* plan);
 
 /* ---------------------------------------------------------------------------
  * Batched planning: many independent queries (mixed systems, uneven tree
- * capacities) in one persistent launch.  Each workgroup takes the next query
- * from a device work queue and runs that query's AO-x loop alone (the same
- * iteration as a single-query plan, so every query's results are identical to
- * planning it alone with the same parameters), then takes the next.
+ * capacities) in one persistent launch.  Each workgroup takes the next ticket
+ * (query, team member) from a device work queue and runs its part of that
+ * query's AO-x loop together with the other members of the query's team (the
+ * same iteration as a single-query plan, so every query's results are
+ * identical to planning it alone with the same parameters), then takes the
+ * next ticket.  Tickets go out largest team and most estimated work first.
  * ------------------------------------------------------------------------- */
 typedef struct pakr_batch pakr_batch;
 
@@ -271,8 +273,10 @@ size_t pakr_batch_workspace_size(int n, const pakr_system* sys, const pakr_scene
                                  const pakr_params* params);
 
 /* Validate and set up n queries: query q uses sys[q], scenes[q], x_inits[q]
- * (host pointer to d floats), goals[q], params[q] (grid and
- * workgroups_per_cu are ignored; lanes_per_candidate 0 means 1 here).  The
+ * (host pointer to d floats), goals[q], params[q] (here `grid` is the query's
+ * team size: the workgroups of the batch launch that plan it together, 1..16,
+ * 0 = its share of the batch's estimated work; workgroups_per_cu is ignored;
+ * lanes_per_candidate 0 means 1).  The
  * workspace rules are those of pakr_plan_init.  On a validation error the
  * message names the query.  Enqueues on `stream`. */
 int pakr_batch_init(int n, const pakr_system* sys, const pakr_scene* scenes,
@@ -300,6 +304,9 @@ int pakr_batch_extract_path(pakr_batch* batch, int q, float* states, float* acti
 
 /* Workgroups of the batch launch (queries run concurrently). */
 int pakr_batch_grid(const pakr_batch* batch);
+
+/* Team size of query q (workgroups that plan it together); 0 if q is invalid. */
+int pakr_batch_team(const pakr_batch* batch, int q);
 
 /* Message for the last error of `batch`. */
 const char* pakr_batch_last_error(const pakr_batch* batch);

@@ -479,8 +479,10 @@ struct pakr_batch {
   void* ws = nullptr;
   bool own_ws = false;
   std::vector<KArgs> args;
-  std::vector<int> order;  // device queue position -> query (longest estimated work first)
+  std::vector<int> team;   // workgroups per query
   KArgs* d_args = nullptr;
+  int* d_tickets = nullptr;
+  int n_tickets = 0;
   int* d_queue = nullptr;
   size_t shmem = 0;
   hipStream_t cap_stream = nullptr;
@@ -787,27 +789,37 @@ const char* pakr_error_string(int code) {
 
 namespace {
 
-// Relative work of one iteration of a query: the rollout arithmetic of its B
-// candidates plus the nearest-neighbour scan of K targets over a tree taken
-// as half of what one round can grow (a scheduling estimate only).
+// Relative cost of one iteration of a query on one workgroup, for scheduling
+// only: a fixed part (barriers, scans, bookkeeping), the rollout of the B
+// candidates (an evaluation of f counted with its sincos/tan calls at ~40
+// operations each) and the NN scan of K targets over a tree taken as 2 % of
+// what one round could insert.  Calibrated against measured iteration times
+// (quadrotor ~2.6 ms, 3D double integrator ~0.15 ms on one workgroup).
 double query_work(const DevProblem& Q) {
-  const double f_eval = Q.system == PAKR_QUAD ? 84.0 : (Q.system == PAKR_CAR ? 8.0 : 0.0);
+  const double f_eval = Q.system == PAKR_QUAD ? 204.0 : (Q.system == PAKR_CAR ? 128.0 : 0.0);
   const double roll =
       (double)Q.B * Q.T * (12.0 * Q.d + 4.0 * f_eval + 3.0 * Q.npos * (Q.n_box + Q.n_sph));
-  const double tree = 0.5 * std::min((double)Q.n_cap, (double)Q.B * Q.max_iters_per_round);
-  return roll + (double)Q.K * tree * 3.0 * Q.d;
+  const double tree = std::min((double)Q.n_cap, 0.02 * Q.B * Q.max_iters_per_round);
+  return 1.7e7 + roll + (double)Q.K * tree * 3.0 * Q.d;
 }
 
 int batch_lanes(const pakr_params& p) { return p.lanes_per_candidate > 0 ? p.lanes_per_candidate : 1; }
 
+// Workgroups that share one query of a batch ("team"): at most TEAM_MAX.
+constexpr int TEAM_MAX = 16;
+
 // Offsets of the batch workspace: queue word, argument table, then one
 // single-workgroup query layout after another.
+// Batch workspace: queue word, the argument table, the ticket table, then each
+// query's regions, sized for a team of up to TEAM_MAX workgroups.
+size_t batch_tickets_offset(int n) { return 256 + align_up(sizeof(KArgs) * (size_t)n); }
+
 size_t batch_layout(int n, const pakr_system* sys, const pakr_scene* sc, const pakr_params* prm,
                     std::vector<size_t>* bases, std::vector<Layout>* layouts) {
-  size_t off = 256 + align_up(sizeof(KArgs) * (size_t)n);
+  size_t off = batch_tickets_offset(n) + align_up(sizeof(int) * (size_t)n * TEAM_MAX);
   for (int q = 0; q < n; ++q) {
     const int of = obs_floats_of(sc[q].npos, sc[q].n_box, sc[q].n_sphere);
-    const Layout L = make_layout(sys[q].d, sys[q].m, prm[q], 1, of, batch_lanes(prm[q]));
+    const Layout L = make_layout(sys[q].d, sys[q].m, prm[q], TEAM_MAX, of, batch_lanes(prm[q]));
     if (bases) bases->push_back(off);
     if (layouts) layouts->push_back(L);
     off = align_up(off + L.total);
@@ -842,6 +854,9 @@ int pakr_batch_init(int n, const pakr_system* sys, const pakr_scene* scenes,
     int code = PAKR_OK;
     const std::string msg = validate(&sys[q], &scenes[q], x_inits[q], &goals[q], &params[q], &code);
     if (code != PAKR_OK) return bfail(nullptr, code, "query " + std::to_string(q) + ": " + msg);
+    if (params[q].grid > TEAM_MAX)
+      return bfail(nullptr, PAKR_E_INVALID_ARG,
+                   "query " + std::to_string(q) + ": team size (grid) must be <= 16 in a batch");
     const int L = batch_lanes(params[q]);
     if ((params[q].B + NT / L - 1) / (NT / L) > MAX_GR)
       return bfail(nullptr, PAKR_E_INVALID_ARG,
@@ -867,7 +882,7 @@ int pakr_batch_init(int n, const pakr_system* sys, const pakr_scene* scenes,
     delete bt;
     return rc;
   }
-  bt->G = std::max(1, std::min(n, per_cu * di.n_cu));
+  const int g_full = std::max(1, per_cu * di.n_cu);  // co-resident workgroups
 
   std::vector<size_t> bases;
   std::vector<Layout> layouts;
@@ -892,25 +907,57 @@ int pakr_batch_init(int n, const pakr_system* sys, const pakr_scene* scenes,
   char* base = static_cast<char*>(bt->ws);
   bt->d_queue = reinterpret_cast<int*>(base);
   bt->d_args = reinterpret_cast<KArgs*>(base + 256);
-  bt->args.resize((size_t)n);
+  bt->d_tickets = reinterpret_cast<int*>(base + batch_tickets_offset(n));
+  // Team sizes: params.grid if set, else the query's share of the estimated
+  // work of the whole batch in workgroups (at least 1, at most TEAM_MAX).
+  std::vector<double> work((size_t)n);
+  double total = 0.0;
   for (int q = 0; q < n; ++q) {
     const DevProblem Q = make_problem(sys[q], scenes[q], goals[q], params[q], 1, batch_lanes(params[q]));
+    work[q] = query_work(Q);
+    total += work[q];
+  }
+  bt->team.resize((size_t)n);
+  for (int q = 0; q < n; ++q) {
+    int g = params[q].grid;
+    if (g <= 0) g = (int)std::lround(work[q] * g_full / total);
+    bt->team[q] = std::max(1, std::min(std::min(g, TEAM_MAX), g_full));
+  }
+  int n_team_wg = 0;
+  for (int q = 0; q < n; ++q) n_team_wg += bt->team[q];
+  bt->G = std::min(n_team_wg, g_full);
+  bt->args.resize((size_t)n);
+  for (int q = 0; q < n; ++q) {
+    const DevProblem Q = make_problem(sys[q], scenes[q], goals[q], params[q], bt->team[q],
+                                      batch_lanes(params[q]));
     bt->args[q] = make_args(Q, base + bases[q], layouts[q]);
-    e = upload_query(bt->args[q], pack_obstacles(scenes[q]), x_inits[q], 1, bt->stream);
+    e = upload_query(bt->args[q], pack_obstacles(scenes[q]), x_inits[q], TEAM_MAX, bt->stream);
     if (e != hipSuccess) {
       int rc = bhip_fail(nullptr, e, "upload query");
       pakr_batch_destroy(bt);
       return rc;
     }
   }
-  // Longest-processing-time-first: the queue hands out the queries with the
-  // most estimated work per round first, so the long ones do not start last.
-  std::vector<double> work((size_t)n);
-  for (int q = 0; q < n; ++q) work[q] = query_work(bt->args[q].P);
-  bt->order.resize((size_t)n);
-  for (int q = 0; q < n; ++q) bt->order[q] = q;
-  std::stable_sort(bt->order.begin(), bt->order.end(),
-                   [&](int a, int b) { return work[a] > work[b]; });
+  // Tickets in longest-processing-time-first order: bigger teams, then more
+  // estimated work, come first, so the long queries start at the launch.  A
+  // team's tickets are consecutive; ticket = query << 5 | member.
+  std::vector<int> order((size_t)n);
+  for (int q = 0; q < n; ++q) order[q] = q;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return bt->team[a] != bt->team[b] ? bt->team[a] > bt->team[b] : work[a] > work[b];
+  });
+  std::vector<int> tickets;
+  for (int q : order)
+    for (int m = 0; m < bt->team[q]; ++m) tickets.push_back(q << 5 | m);
+  bt->n_tickets = (int)tickets.size();
+  e = hipMemcpyAsync(bt->d_tickets, tickets.data(), sizeof(int) * tickets.size(),
+                     hipMemcpyHostToDevice, bt->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(bt->stream);  // pageable source
+  if (e != hipSuccess) {
+    int rc = bhip_fail(nullptr, e, "upload tickets");
+    pakr_batch_destroy(bt);
+    return rc;
+  }
   *out = bt;
   return PAKR_OK;
 }
@@ -922,16 +969,15 @@ int batch_enqueue(pakr_batch* bt, double budget_ms, int max_rounds, long long ma
                   hipStream_t s, bool upload) {
   if (upload) {
     for (auto& a : bt->args) set_limits(a, max_iters, max_rounds, budget_ms, bt->ticks_per_ms);
-    std::vector<KArgs> table(bt->args.size());
-    for (size_t i = 0; i < table.size(); ++i) table[i] = bt->args[(size_t)bt->order[i]];
-    hipError_t e = hipMemcpyAsync(bt->d_args, table.data(), sizeof(KArgs) * table.size(),
+    hipError_t e = hipMemcpyAsync(bt->d_args, bt->args.data(), sizeof(KArgs) * bt->args.size(),
                                   hipMemcpyHostToDevice, bt->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(bt->stream);  // pageable source
     if (e != hipSuccess) return bhip_fail(bt, e, "upload batch arguments");
   }
   hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, bt->d_queue);
   hipLaunchKernelGGL(k_batch, dim3(bt->G), dim3(NT), bt->shmem, s,
-                     static_cast<const KArgs*>(bt->d_args), bt->nq, bt->d_queue);
+                     static_cast<const KArgs*>(bt->d_args), static_cast<const int*>(bt->d_tickets),
+                     bt->n_tickets, bt->d_queue);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return bhip_fail(bt, e, "batch launch");
   return PAKR_OK;
@@ -1039,6 +1085,10 @@ int pakr_batch_extract_path(pakr_batch* bt, int q, float* states, float* actions
 }
 
 int pakr_batch_grid(const pakr_batch* bt) { return bt ? bt->G : 0; }
+
+int pakr_batch_team(const pakr_batch* bt, int q) {
+  return (bt && q >= 0 && q < bt->nq) ? bt->team[(size_t)q] : 0;
+}
 
 const char* pakr_batch_last_error(const pakr_batch* bt) {
   return bt ? bt->err.c_str() : g_init_error.c_str();

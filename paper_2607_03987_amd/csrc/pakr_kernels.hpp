@@ -741,7 +741,14 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
 // Many queries in one launch: each workgroup takes the next query from a
 // device work queue and plans it alone (no grid barrier), until the queue is
 // empty.  Queries may mix systems and tree capacities.
-__global__ __launch_bounds__(NT) void k_batch(const KArgs* __restrict__ qs, int nq, int* queue) {
+// Persistent batch: each workgroup takes the next ticket (query, member) from
+// the device queue and runs that member's part of the query's AO-x loop with
+// its teammates (consecutive tickets), then takes the next ticket.  Only
+// running workgroups take tickets, so a team's members are co-resident, and
+// every team below the first untaken ticket is complete and can progress.
+__global__ __launch_bounds__(NT) void k_batch(const KArgs* __restrict__ qs,
+                                              const int* __restrict__ tickets, int n_tickets,
+                                              int* queue) {
   extern __shared__ float s_obs[];
   __shared__ __align__(16) float s_tile[PAKR_MAX_D * TILE];
   __shared__ unsigned long long s_best[NT];
@@ -757,16 +764,20 @@ __global__ __launch_bounds__(NT) void k_batch(const KArgs* __restrict__ qs, int 
                             s_misc);
   while (true) {
     __syncthreads();  // everyone has read the previous s_q
-    if (threadIdx.x == 0) s_q = atomicAdd(queue, 1);
+    if (threadIdx.x == 0) {
+      const int t = atomicAdd(queue, 1);
+      s_q = t < n_tickets ? tickets[t] : -1;
+    }
     __syncthreads();
-    const int q = __builtin_amdgcn_readfirstlane(s_q);
-    if (q >= nq) break;
-    const KArgs& a = qs[q];
+    const int ticket = __builtin_amdgcn_readfirstlane(s_q);
+    if (ticket < 0) break;
+    const KArgs& a = qs[ticket >> 5];
+    const int member = ticket & 31, team = a.P.G;
     switch (a.P.system) {
-      case PAKR_DI2: plan_loop<PAKR_DI2, 1>(a, 0, 1, sm); break;
-      case PAKR_DI3: plan_loop<PAKR_DI3, 1>(a, 0, 1, sm); break;
-      case PAKR_CAR: plan_loop<PAKR_CAR, 1>(a, 0, 1, sm); break;
-      default: plan_loop<PAKR_QUAD, 1>(a, 0, 1, sm); break;
+      case PAKR_DI2: plan_loop<PAKR_DI2, 1>(a, member, team, sm); break;
+      case PAKR_DI3: plan_loop<PAKR_DI3, 1>(a, member, team, sm); break;
+      case PAKR_CAR: plan_loop<PAKR_CAR, 1>(a, member, team, sm); break;
+      default: plan_loop<PAKR_QUAD, 1>(a, member, team, sm); break;
     }
   }
 }

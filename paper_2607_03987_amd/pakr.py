@@ -39,6 +39,7 @@ EXPORTED = ["pakr_workspace_size", "pakr_plan_init", "pakr_plan_destroy", "pakr_
             "pakr_batch_workspace_size", "pakr_batch_init", "pakr_batch_replan",
             "pakr_batch_graph_capture", "pakr_batch_graph_launch", "pakr_batch_status",
             "pakr_batch_solutions", "pakr_batch_extract_path", "pakr_batch_grid",
+            "pakr_batch_team",
             "pakr_batch_last_error", "pakr_batch_destroy",
             "pakr_refiner_init", "pakr_refiner_set_params", "pakr_rollout_ckpt_bytes",
             "pakr_rollout_fwd", "pakr_rollout_bwd", "pakr_refine_step", "pakr_check_path",
@@ -168,6 +169,8 @@ def load():
         L.pakr_batch_extract_path.restype = C.c_int
         L.pakr_batch_grid.argtypes = [vp]
         L.pakr_batch_grid.restype = C.c_int
+        L.pakr_batch_team.argtypes = [vp, C.c_int]
+        L.pakr_batch_team.restype = C.c_int
         L.pakr_batch_last_error.argtypes = [vp]
         L.pakr_batch_last_error.restype = C.c_char_p
         L.pakr_batch_destroy.argtypes = [vp]
@@ -411,10 +414,11 @@ def _bcheck(rc: int, handle=None):
 class CBatch:
     """The C arrays of a list of Problems (holds the host arrays alive)."""
 
-    def __init__(self, probs, lanes: int = 0):
+    def __init__(self, probs, lanes: int = 0, teams=0):
         self.probs = list(probs)
         n = self.n = len(self.probs)
-        self.qs = [CQuery(p, lanes=lanes) for p in self.probs]
+        teams = [int(teams)] * n if isinstance(teams, int) else [int(t) for t in teams]
+        self.qs = [CQuery(p, lanes=lanes, grid=t) for p, t in zip(self.probs, teams)]
         self.sys = (System * n)(*[q.system for q in self.qs])
         self.sc = (Scene * n)(*[q.scene for q in self.qs])
         self.goal = (Goal * n)(*[q.goal for q in self.qs])
@@ -435,19 +439,21 @@ def batch_init(cb: CBatch, d_workspace: int, ws_bytes: int, stream: int) -> int:
 
 
 class BatchPlan:
-    """Many queries planned by one persistent launch (one workgroup per query).
+    """Many queries planned by one persistent launch (a team of workgroups per query).
 
     Query q's results equal those of Plan(probs[q], lanes=...) with the same
-    parameters; the workspace is one torch uint8 tensor.
+    parameters; the workspace is one torch uint8 tensor.  `teams` (an int for
+    every query or a list) fixes the team sizes; 0 lets the library size each
+    team by the query's share of the estimated work.
     """
 
-    def __init__(self, probs, lanes: int = 0, device=None):
+    def __init__(self, probs, lanes: int = 0, device=None, teams=0):
         import torch
 
         if not torch.cuda.is_available():
             raise RuntimeError("libpakr needs a ROCm GPU; none is visible")
         self.torch = torch
-        self.cb = CBatch(probs, lanes=lanes)
+        self.cb = CBatch(probs, lanes=lanes, teams=teams)
         self.probs = self.cb.probs
         nbytes = batch_workspace_size(self.cb)
         if nbytes == 0:
@@ -475,6 +481,9 @@ class BatchPlan:
     @property
     def grid(self) -> int:
         return int(load().pakr_batch_grid(self.h))
+
+    def team(self, q: int) -> int:
+        return int(load().pakr_batch_team(self.h, int(q)))
 
     def replan(self, budget_ms: float = 0.0, max_rounds: int = 0, max_iters: int = 0):
         _bcheck(load().pakr_batch_replan(self.h, float(budget_ms), int(max_rounds),

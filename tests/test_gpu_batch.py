@@ -1,7 +1,7 @@
 """Batched multi-query planning (GPU tests).
 
 One persistent launch plans many queries of mixed systems and uneven tree
-capacities, one workgroup per query.  Every query's results must be
+capacities, each by a team of one or more workgroups.  Every query's results must be
 bit-identical to planning it alone with the same parameters (the single-query
 path is itself held to the FP64 reference by test_gpu_parity.py), and a
 captured hipGraph of the launch must replay to the same state as direct calls.
@@ -22,10 +22,16 @@ def small_batch(n, seed=0, iters_per_round=30):
             for p in probs]
 
 
-def test_batch_equals_single_query_plans():
+TEAMS = {"single": 1, "auto": 0, "mixed": [1, 2, 3, 16, 1, 4, 2, 1, 5]}
+
+
+@pytest.mark.parametrize("teams", list(TEAMS))
+def test_batch_equals_single_query_plans(teams):
     probs = small_batch(9)
-    print("case batch of 9 mixed queries, 2 rounds", flush=True)
-    bp = pakr.BatchPlan(probs, lanes=1)
+    print(f"case batch of 9 mixed queries, 2 rounds, teams {teams}", flush=True)
+    bp = pakr.BatchPlan(probs, lanes=1, teams=TEAMS[teams])
+    if teams == "mixed":
+        assert [bp.team(q) for q in range(9)] == TEAMS["mixed"]
     bp.replan(max_rounds=2)
     for q, prob in enumerate(probs):
         pl = pakr.Plan(prob, lanes=1)
