@@ -1147,6 +1147,7 @@ RefineParams to_device(const pakr_refine_params& rp) {
   R.w_c = rp.w_collision;
   R.beta = rp.beta;
   R.delta = rp.delta;
+  R.inv_beta = rp.beta > 0.0f ? 1.0f / rp.beta : 0.0f;
   for (int c = 0; c < PAKR_MAX_M; ++c) {
     R.u_ref[c] = rp.u_ref[c];
     R.u_scale[c] = rp.u_scale[c] > 0.0f ? rp.u_scale[c] : 1.0f;

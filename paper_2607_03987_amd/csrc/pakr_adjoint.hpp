@@ -24,7 +24,7 @@
 namespace pakr {
 
 struct RefineParams {
-  float w_u, w_g, w_c, beta, delta;
+  float w_u, w_g, w_c, beta, delta, inv_beta;
   float u_ref[PAKR_MAX_M], u_scale[PAKR_MAX_M];
 };
 
@@ -43,13 +43,22 @@ struct TrajArgs {
   float* cost;         // [n_traj] the planner's cost of the trajectory
 };
 
-__device__ __forceinline__ float softplus_b(float z, float beta) {
-  const float bz = beta * z;
-  return bz > 0.0f ? z + log1pf(expf(-bz)) / beta : log1pf(expf(bz)) / beta;
+// softplus_beta(z) = log(1 + exp(beta z)) / beta and its derivative
+// sigmoid(beta z).  A term with beta z < SP_CUT is taken as zero (its value is
+// below e^-30 / beta), so inactive terms cost a compare: for the state-bound
+// terms, which every lane evaluates on the same state, the branch is uniform.
+constexpr float SP_CUT = -30.0f;
+
+__device__ __forceinline__ float softplus_b(float z, const RefineParams& R) {
+  const float bz = R.beta * z;
+  if (bz < SP_CUT) return 0.0f;
+  return bz > 0.0f ? z + log1pf(expf(-bz)) * R.inv_beta : log1pf(expf(bz)) * R.inv_beta;
 }
 
-__device__ __forceinline__ float sigmoid_b(float z, float beta) {
-  return 1.0f / (1.0f + expf(-beta * z));
+__device__ __forceinline__ float sigmoid_b(float z, const RefineParams& R) {
+  const float bz = R.beta * z;
+  if (bz < SP_CUT) return 0.0f;
+  return 1.0f / (1.0f + expf(-bz));
 }
 
 __device__ __forceinline__ float wave_sum(float v) {
@@ -64,7 +73,6 @@ template <int NP>
 __device__ __forceinline__ float obstacle_penalty(const DevProblem& P, const RefineParams& R,
                                                   const float* s_obs, const float* x, float* grad,
                                                   int first, int stride) {
-  const float beta = R.beta;
   float pen = 0.0f;
   for (int b = first; b < P.n_box; b += stride) {
     const float* o = s_obs + b * (2 * NP);
@@ -85,9 +93,9 @@ __device__ __forceinline__ float obstacle_penalty(const DevProblem& P, const Ref
     // signed distance to the box: outside part plus (inside) the largest face gap
     const float so = outside > 0.0f ? sqrtf(outside) : 0.0f;
     const float sd = so + (inner < 0.0f ? inner : 0.0f);
-    pen += softplus_b(R.delta - sd, beta);
+    pen += softplus_b(R.delta - sd, R);
     if (grad) {
-      const float dsd = -sigmoid_b(R.delta - sd, beta);
+      const float dsd = -sigmoid_b(R.delta - sd, R);
 #pragma unroll
       for (int c = 0; c < NP; ++c) {
         float dq = 0.0f;
@@ -108,9 +116,9 @@ __device__ __forceinline__ float obstacle_penalty(const DevProblem& P, const Ref
     }
     const float dist = sqrtf(r2);
     const float sd = dist - sqrtf(o[NP]);  // the record holds r^2
-    pen += softplus_b(R.delta - sd, beta);
+    pen += softplus_b(R.delta - sd, R);
     if (grad && dist > 0.0f) {
-      const float dsd = -sigmoid_b(R.delta - sd, beta) / dist;
+      const float dsd = -sigmoid_b(R.delta - sd, R) / dist;
 #pragma unroll
       for (int c = 0; c < NP; ++c) grad[c] += dsd * e[c];
     }
@@ -123,23 +131,22 @@ template <int SYS>
 __device__ __forceinline__ float bound_penalty(const DevProblem& P, const RefineParams& R,
                                                const float* s_val, const float* x, float* grad) {
   constexpr int D = Sys<SYS>::D, NP = Sys<SYS>::P;
-  const float beta = R.beta;
   float pen = 0.0f;
 #pragma unroll
   for (int c = 0; c < NP; ++c) {
-    pen += softplus_b(x[c] - s_val[3 + c], beta) + softplus_b(s_val[c] - x[c], beta);
-    if (grad) grad[c] += sigmoid_b(x[c] - s_val[3 + c], beta) - sigmoid_b(s_val[c] - x[c], beta);
+    pen += softplus_b(x[c] - s_val[3 + c], R) + softplus_b(s_val[c] - x[c], R);
+    if (grad) grad[c] += sigmoid_b(x[c] - s_val[3 + c], R) - sigmoid_b(s_val[c] - x[c], R);
   }
 #pragma unroll
   for (int i = NP; i < D; ++i) {
     const float lo = s_val[6 + i], hi = s_val[18 + i];
     if (hi < INFINITY) {
-      pen += softplus_b(x[i] - hi, beta);
-      if (grad) grad[i] += sigmoid_b(x[i] - hi, beta);
+      pen += softplus_b(x[i] - hi, R);
+      if (grad) grad[i] += sigmoid_b(x[i] - hi, R);
     }
     if (lo > -INFINITY) {
-      pen += softplus_b(lo - x[i], beta);
-      if (grad) grad[i] -= sigmoid_b(lo - x[i], beta);
+      pen += softplus_b(lo - x[i], R);
+      if (grad) grad[i] -= sigmoid_b(lo - x[i], R);
     }
   }
   if constexpr (SYS == PAKR_DI2 || SYS == PAKR_DI3) {
@@ -148,9 +155,9 @@ __device__ __forceinline__ float bound_penalty(const DevProblem& P, const Refine
 #pragma unroll
       for (int c = 0; c < NP; ++c) v2 += x[NP + c] * x[NP + c];
       const float vn = sqrtf(v2);
-      pen += softplus_b(vn - P.vnorm_max, beta);
+      pen += softplus_b(vn - P.vnorm_max, R);
       if (grad && vn > 0.0f) {
-        const float g = sigmoid_b(vn - P.vnorm_max, beta) / vn;
+        const float g = sigmoid_b(vn - P.vnorm_max, R) / vn;
 #pragma unroll
         for (int c = 0; c < NP; ++c) grad[NP + c] += g * x[NP + c];
       }
@@ -166,7 +173,8 @@ __device__ __forceinline__ float wave_penalty(const DevProblem& P, const RefineP
                                               const float* x, int lane) {
   constexpr int NP = Sys<SYS>::P;
   const float part = obstacle_penalty<NP>(P, R, s_obs, x, nullptr, lane, WAVE);
-  return wave_sum(part) + bound_penalty<SYS>(P, R, s_val, x, nullptr);
+  const float obs = __ballot(part != 0.0f) != 0ull ? wave_sum(part) : 0.0f;
+  return obs + bound_penalty<SYS>(P, R, s_val, x, nullptr);
 }
 
 // d pen / dx for the whole wave, added to g on every lane.
@@ -178,16 +186,19 @@ __device__ __forceinline__ void wave_penalty_grad(const DevProblem& P, const Ref
   float gp[NP];
 #pragma unroll
   for (int c = 0; c < NP; ++c) gp[c] = 0.0f;
-  obstacle_penalty<NP>(P, R, s_obs, x, gp, lane, WAVE);
+  const float part = obstacle_penalty<NP>(P, R, s_obs, x, gp, lane, WAVE);
+  if (__ballot(part != 0.0f) != 0ull) {  // some lane has an active obstacle term
 #pragma unroll
-  for (int c = 0; c < NP; ++c) g[c] += wave_sum(gp[c]);
+    for (int c = 0; c < NP; ++c) g[c] += wave_sum(gp[c]);
+  }
   bound_penalty<SYS>(P, R, s_val, x, g);
 }
 
-// Vector-Jacobian products of f (Eq. (1)): gx += (df/dx)^T w, gu += (df/du)^T w.
+// Vector-Jacobian products of f (Eq. (1)): gx += (df/dx)^T w, gu += (df/du)^T w,
+// at a state whose trigonometric values are tg.
 template <int SYS>
-__device__ __forceinline__ void dynamics_vjp(const DevProblem& P, const float* x, const float* w,
-                                             float* gx, float* gu) {
+__device__ __forceinline__ void dynamics_vjp(const DevProblem& P, const float* x, const Trig& tg,
+                                             const float* w, float* gx, float* gu) {
   if constexpr (SYS == PAKR_DI2 || SYS == PAKR_DI3) {
     constexpr int Dp = Sys<SYS>::P;
 #pragma unroll
@@ -196,9 +207,8 @@ __device__ __forceinline__ void dynamics_vjp(const DevProblem& P, const float* x
       gu[a] += w[Dp + a];  // velocity' = control
     }
   } else if constexpr (SYS == PAKR_CAR) {
-    float s, c;
-    sincosf(x[2], &s, &c);
-    const float v = x[3], t = tanf(x[4]), invL = 1.0f / P.dyn[0];
+    const float s = tg.s[0], c = tg.c[0];
+    const float v = x[3], t = tg.t, invL = 1.0f / P.dyn[0];
     gx[2] += -v * s * w[0] + v * c * w[1];
     gx[3] += c * w[0] + s * w[1] + t * invL * w[2];
     gx[4] += v * (1.0f + t * t) * invL * w[2];
@@ -207,10 +217,8 @@ __device__ __forceinline__ void dynamics_vjp(const DevProblem& P, const float* x
   } else {
     const float inv_m = 1.0f / P.dyn[0], g = P.dyn[1];
     const float Ix = P.dyn[2], Iy = P.dyn[3], Iz = P.dyn[4];
-    float sph, cph, sth, cth, sps, cps;
-    sincosf(x[3], &sph, &cph);
-    sincosf(x[4], &sth, &cth);
-    sincosf(x[5], &sps, &cps);
+    const float sph = tg.s[0], cph = tg.c[0], sth = tg.s[1], cth = tg.c[1];
+    const float sps = tg.s[2], cps = tg.c[2];
     const float v0 = x[6], v1 = x[7], v2 = x[8];
     const float p = x[9], q = x[10], r = x[11];
     const float r00 = cps * cth, r01 = cps * sth * sph - sps * cph, r02 = cps * sth * cph + sps * sph;
@@ -267,18 +275,23 @@ __device__ __forceinline__ void rk4_step_vjp(const DevProblem& P, const float* x
                                              float h, float* lam, float* gu) {
   constexpr int D = Sys<SYS>::D;
   float k[3][D], xs[4][D];
+  Trig tg[4];
   const float hh = 0.5f * h;
 #pragma unroll
   for (int i = 0; i < D; ++i) xs[0][i] = x[i];
-  dynamics<SYS>(P, xs[0], u, k[0]);
+  tg[0] = trig_of<SYS>(xs[0]);
+  dynamics_trig<SYS>(P, xs[0], u, tg[0], k[0]);
 #pragma unroll
   for (int i = 0; i < D; ++i) xs[1][i] = x[i] + hh * k[0][i];
-  dynamics<SYS>(P, xs[1], u, k[1]);
+  tg[1] = trig_of<SYS>(xs[1]);
+  dynamics_trig<SYS>(P, xs[1], u, tg[1], k[1]);
 #pragma unroll
   for (int i = 0; i < D; ++i) xs[2][i] = x[i] + hh * k[1][i];
-  dynamics<SYS>(P, xs[2], u, k[2]);
+  tg[2] = trig_of<SYS>(xs[2]);
+  dynamics_trig<SYS>(P, xs[2], u, tg[2], k[2]);
 #pragma unroll
   for (int i = 0; i < D; ++i) xs[3][i] = x[i] + h * k[2][i];
+  tg[3] = trig_of<SYS>(xs[3]);
   // x_{n+1} = x + h/6 (k1 + 2 k2 + 2 k3 + k4); stage s (0-based) evaluates f
   // at x + c_s k_{s-1} with c = (h/2, h/2, h)
   const float h6 = h * (1.0f / 6.0f);
@@ -298,7 +311,7 @@ __device__ __forceinline__ void rk4_step_vjp(const DevProblem& P, const float* x
       gk[i] = wk[s] * lam[i] + carry[i];
       gxs[i] = 0.0f;
     }
-    dynamics_vjp<SYS>(P, xs[s], gk, gxs, gu);
+    dynamics_vjp<SYS>(P, xs[s], tg[s], gk, gxs, gu);
 #pragma unroll
     for (int i = 0; i < D; ++i) {
       carry[i] = s > 0 ? cs[s - 1] * gxs[i] : 0.0f;

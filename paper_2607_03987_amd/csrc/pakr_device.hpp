@@ -136,10 +136,31 @@ template <> struct Sys<PAKR_DI3> { static constexpr int D = 6, M = 3, P = 3, CH 
 template <> struct Sys<PAKR_CAR> { static constexpr int D = 5, M = 2, P = 2, CH = 8; };
 template <> struct Sys<PAKR_QUAD> { static constexpr int D = 12, M = 4, P = 3, CH = 4; };
 
-// x' = f(x, u), Eq. (1).
+// The trigonometric values f needs at one state: the car's heading sine and
+// cosine and steering tangent, the quadrotor's roll, pitch and yaw sines and
+// cosines.  Computed once per evaluation (and, in the adjoint, shared between
+// an RK4 stage's evaluation of f and its vector-Jacobian product).
+struct Trig {
+  float s[3], c[3], t;
+};
+
 template <int SYS>
-__device__ __forceinline__ void dynamics(const DevProblem& P, const float* x, const float* u,
-                                         float* xd) {
+__device__ __forceinline__ Trig trig_of(const float* x) {
+  Trig g;
+  if constexpr (SYS == PAKR_CAR) {
+    sincosf(x[2], &g.s[0], &g.c[0]);
+    g.t = tanf(x[4]);
+  } else if constexpr (SYS == PAKR_QUAD) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) sincosf(x[3 + k], &g.s[k], &g.c[k]);
+  }
+  return g;
+}
+
+// x' = f(x, u), Eq. (1), given the state's trigonometric values.
+template <int SYS>
+__device__ __forceinline__ void dynamics_trig(const DevProblem& P, const float* x, const float* u,
+                                              const Trig& tg, float* xd) {
   if constexpr (SYS == PAKR_DI2 || SYS == PAKR_DI3) {
     constexpr int Dp = Sys<SYS>::P;
 #pragma unroll
@@ -148,22 +169,19 @@ __device__ __forceinline__ void dynamics(const DevProblem& P, const float* x, co
       xd[Dp + a] = u[a];
     }
   } else if constexpr (SYS == PAKR_CAR) {
-    float s, c;
-    sincosf(x[2], &s, &c);
+    const float s = tg.s[0], c = tg.c[0];
     const float v = x[3];
     xd[0] = v * c;
     xd[1] = v * s;
-    xd[2] = v * tanf(x[4]) * (1.0f / P.dyn[0]);
+    xd[2] = v * tg.t * (1.0f / P.dyn[0]);
     xd[3] = u[0];
     xd[4] = u[1];
   } else {
     // quadrotor, Z-Y-X Euler angles; body-frame velocity (ub,vb,wb), rates (p,q,r)
     const float inv_m = 1.0f / P.dyn[0], g = P.dyn[1];
     const float Ix = P.dyn[2], Iy = P.dyn[3], Iz = P.dyn[4];
-    float sph, cph, sth, cth, sps, cps;
-    sincosf(x[3], &sph, &cph);
-    sincosf(x[4], &sth, &cth);
-    sincosf(x[5], &sps, &cps);
+    const float sph = tg.s[0], cph = tg.c[0], sth = tg.s[1], cth = tg.c[1];
+    const float sps = tg.s[2], cps = tg.c[2];
     const float ub = x[6], vb = x[7], wb = x[8];
     const float p = x[9], q = x[10], r = x[11];
     // rotation body -> world, R = Rz(yaw) Ry(pitch) Rx(roll)
@@ -187,6 +205,13 @@ __device__ __forceinline__ void dynamics(const DevProblem& P, const float* x, co
     xd[10] = (u[2] - (Ix - Iz) * r * p) / Iy;
     xd[11] = (u[3] - (Iy - Ix) * p * q) / Iz;
   }
+}
+
+// x' = f(x, u), Eq. (1).
+template <int SYS>
+__device__ __forceinline__ void dynamics(const DevProblem& P, const float* x, const float* u,
+                                         float* xd) {
+  dynamics_trig<SYS>(P, x, u, trig_of<SYS>(x), xd);
 }
 
 // One classical RK4 step with the control held (Sec. IV-A).
