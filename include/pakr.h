@@ -142,7 +142,7 @@ typedef struct pakr_params {
   int max_iters_per_round;         /* a round with no solution ends after this many     */
   int grid;                        /* workgroups of the persistent launch, 0 = auto     */
   int max_path_edges;              /* capacity of the stored best path, 0 = 4096        */
-  int lanes_per_candidate;         /* 1, 2, 4 or 8 lanes share one rollout and split its
+  int lanes_per_candidate;         /* 1, 2, 4, 8 or 16 lanes share one rollout and split its
                                       obstacle tests; 0 = auto (from the obstacle count) */
   int workgroups_per_cu;           /* with grid = 0: launch this many workgroups per CU
                                       and reserve LDS so that no CU holds more; 0 = 1    */

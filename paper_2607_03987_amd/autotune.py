@@ -11,7 +11,7 @@ workgroups per CU for the 3D double-integrator AO-x query, scored by
 expansions per second.
 
 The table is written to tuned.json next to this file; bench.py reads it.
-Run: python -m paper_2607_03987_amd.autotune   (needs a GPU)
+Run: python -m paper_2607_03987_amd.autotune [--out PATH]   (needs a GPU)
 """
 from __future__ import annotations
 
@@ -94,7 +94,7 @@ def tune_batch(torch, n_per_system=48, iters_per_round=50, log=print) -> dict:
 
 def tune_single(torch, budget_ms=100.0, log=print) -> dict:
     best = None
-    for L in (2, 4, 8):
+    for L in (2, 4, 8, 16):
         for k in (1, 2):
             plan = pakr.Plan(W.config_c2(seed=0), lanes=L, wg_per_cu=k)
             plan.replan(budget_ms=budget_ms)
@@ -109,7 +109,13 @@ def tune_single(torch, budget_ms=100.0, log=print) -> dict:
 
 
 def main():
+    import argparse
+
     import torch
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=TABLE, help="where to write the table")
+    args = ap.parse_args()
 
     if not torch.cuda.is_available():
         raise SystemExit("the autotuner needs a GPU")
@@ -119,7 +125,7 @@ def main():
     table.update(tune_batch(torch))
     table["device"] = torch.cuda.get_device_name(0)
     table["seconds"] = round(time.time() - t0, 1)
-    with open(TABLE, "w") as f:
+    with open(args.out, "w") as f:
         json.dump(table, f, indent=1)
     print(json.dumps(table, indent=1), flush=True)
 

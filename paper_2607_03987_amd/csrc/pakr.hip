@@ -209,8 +209,8 @@ std::string validate(const pakr_system* s, const pakr_scene* sc, const float* x0
   if (p->grid < 0) return "grid must be >= 0";
   if (p->max_path_edges < 0) return "max_path_edges must be >= 0";
   if (p->lanes_per_candidate != 0 && p->lanes_per_candidate != 1 && p->lanes_per_candidate != 2 &&
-      p->lanes_per_candidate != 4 && p->lanes_per_candidate != 8)
-    return "lanes_per_candidate must be 0, 1, 2, 4 or 8";
+      p->lanes_per_candidate != 4 && p->lanes_per_candidate != 8 && p->lanes_per_candidate != 16)
+    return "lanes_per_candidate must be 0, 1, 2, 4, 8 or 16";
   if (p->workgroups_per_cu < 0 || p->workgroups_per_cu > 8) return "workgroups_per_cu must be 0..8";
   m = validate_scene(sc);
   if (!m.empty()) return m;

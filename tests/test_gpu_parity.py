@@ -53,7 +53,7 @@ def test_step_parity_no_obstacles_and_small_grid():
     step_parity(prob, 8, grid=8, log=_log)
 
 
-@pytest.mark.parametrize("lanes", [1, 2, 4, 8])
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16])
 @pytest.mark.parametrize("cfg,kw", [("c2", dict(B=1024, A=8, n_cap=30000)),
                                     ("c4", dict(B=256, A=16, n_cap=30000))])
 def test_step_parity_lanes_per_candidate(cfg, kw, lanes):
