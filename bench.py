@@ -87,7 +87,8 @@ def measured_traffic():
                      float(vals["write_kib_per_dispatch"]) * float(vals["write_factor"]))
 
 
-def batched_vs_plain(torch, pakr, W, n_queries, rounds, iters_per_round, lanes=1, settings=None):
+def batched_vs_plain(torch, pakr, W, n_queries, rounds, iters_per_round, lanes=None,
+                     settings=None):
     """The mixed batch (double integrator, car, quadrotor queries with uneven
     capacities) in one graph-launched persistent kernel, against the same
     queries planned one at a time with the whole GPU each.  Both forms run
@@ -96,8 +97,10 @@ def batched_vs_plain(torch, pakr, W, n_queries, rounds, iters_per_round, lanes=1
     probs = [p.replace(max_iters_per_round=iters_per_round)
              for p in W.config_c5(n_queries=n_queries, seed=0, settings=settings)]
     stream = torch.cuda.current_stream()
-    # batched: one launch, replayed from a captured graph
-    bp = pakr.BatchPlan(probs, lanes=lanes)
+    # batched: one launch, replayed from a captured graph; lanes per candidate
+    # per system from the tuned table
+    lanes = lanes or {}
+    bp = pakr.BatchPlan(probs, lanes=[lanes.get(p.system, 1) for p in probs])
     bp.graph_capture(max_rounds=rounds)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -153,7 +156,7 @@ def batched_vs_plain(torch, pakr, W, n_queries, rounds, iters_per_round, lanes=1
                   "p50_queued_first_ms": pct(p_first, 50), "p99_queued_first_ms": pct(p_first, 99),
                   "expansions": sum(s["expansions"] for s in pst)},
         "settings": {W.SYSTEM_NAMES[k]: v for k, v in (settings or {}).items()},
-        "lanes": lanes,
+        "lanes": {W.SYSTEM_NAMES[k]: v for k, v in lanes.items()},
         "speedup_queries_per_s": sum(p_ms) / batch_ms,
         "queries_with_identical_solutions": f"{same}/{n_queries}",
         "solved": f"{sum(1 for x in b_sols if x)}/{n_queries}",

@@ -1,7 +1,8 @@
 """Autotuner for the planner's launch and batch schedules.
 
 Batched form: for each system of the mixed batch, a sample of that system's
-queries is planned in one batched launch for every candidate (B, A, lanes) --
+queries is planned in one batched launch (teams sized automatically) for every
+candidate (B, A, lanes) --
 B and A on the grid shape of the paper's batch-size / branching-factor study
 (Table 4), lanes = obstacle-test lanes per candidate.  Among the candidates
 that solve at least 95% as many queries as the best one (first solution, one
@@ -47,9 +48,14 @@ def batch_settings(table: dict | None = None) -> dict:
     return out
 
 
-def batch_lanes(table: dict | None = None) -> int:
+def batch_lanes(table: dict | None = None) -> dict:
+    """{system id: lanes per candidate} for the batched form (1 where not tuned)."""
     table = load_table() if table is None else table
-    return int(table.get("batch_lanes", 1))
+    out = {}
+    for name, sid in (("di3", W.DI3), ("car", W.CAR), ("quad", W.QUAD)):
+        ent = table.get("batch", {}).get(name)
+        out[sid] = int(ent.get("lanes", 1)) if ent else 1
+    return out
 
 
 def _score_batch(torch, probs, lanes, iters_per_round):
@@ -69,7 +75,6 @@ def _score_batch(torch, probs, lanes, iters_per_round):
 
 def tune_batch(torch, n_per_system=48, iters_per_round=50, log=print) -> dict:
     res = {}
-    lane_votes = {}
     for name, sid in (("di3", W.DI3), ("car", W.CAR), ("quad", W.QUAD)):
         runs = []
         for B in B_GRID:
@@ -81,15 +86,12 @@ def tune_batch(torch, n_per_system=48, iters_per_round=50, log=print) -> dict:
                     score, solved, ms = _score_batch(torch, probs, L, iters_per_round)
                     log(f"{name} B {B} A {A} lanes {L}: {solved}/{len(probs)} solved in "
                         f"{ms:.1f} ms -> {score:.1f} solved/s")
-                    lane_votes[L] = lane_votes.get(L, 0.0) + score
                     runs.append((score, B, A, L, solved, ms))
         top = max(r[4] for r in runs)
         best = max((r for r in runs if r[4] >= 0.95 * top), key=lambda r: r[0])
         res[name] = dict(B=best[1], A=best[2], lanes=best[3], solved=best[4], makespan_ms=best[5],
                          solved_per_s=best[0], sample=len(probs))
-    # one lane count per batched launch: the one with the best total score
-    lanes = max(lane_votes, key=lane_votes.get)
-    return {"batch": res, "batch_lanes": lanes}
+    return {"batch": res}
 
 
 def tune_single(torch, budget_ms=100.0, log=print) -> dict:

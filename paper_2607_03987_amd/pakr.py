@@ -414,11 +414,12 @@ def _bcheck(rc: int, handle=None):
 class CBatch:
     """The C arrays of a list of Problems (holds the host arrays alive)."""
 
-    def __init__(self, probs, lanes: int = 0, teams=0):
+    def __init__(self, probs, lanes=0, teams=0):
         self.probs = list(probs)
         n = self.n = len(self.probs)
         teams = [int(teams)] * n if isinstance(teams, int) else [int(t) for t in teams]
-        self.qs = [CQuery(p, lanes=lanes, grid=t) for p, t in zip(self.probs, teams)]
+        lanes = [int(lanes)] * n if isinstance(lanes, int) else [int(v) for v in lanes]
+        self.qs = [CQuery(p, lanes=v, grid=t) for p, v, t in zip(self.probs, lanes, teams)]
         self.sys = (System * n)(*[q.system for q in self.qs])
         self.sc = (Scene * n)(*[q.scene for q in self.qs])
         self.goal = (Goal * n)(*[q.goal for q in self.qs])
@@ -442,12 +443,13 @@ class BatchPlan:
     """Many queries planned by one persistent launch (a team of workgroups per query).
 
     Query q's results equal those of Plan(probs[q], lanes=...) with the same
-    parameters; the workspace is one torch uint8 tensor.  `teams` (an int for
-    every query or a list) fixes the team sizes; 0 lets the library size each
-    team by the query's share of the estimated work.
+    parameters; the workspace is one torch uint8 tensor.  `lanes` and `teams`
+    (an int for every query or a list) set the lanes per candidate and the
+    team sizes; team 0 lets the library size each team by the query's share of
+    the estimated work.
     """
 
-    def __init__(self, probs, lanes: int = 0, device=None, teams=0):
+    def __init__(self, probs, lanes=0, device=None, teams=0):
         import torch
 
         if not torch.cuda.is_available():
