@@ -64,6 +64,12 @@ __device__ __forceinline__ unsigned long long pack_key(float v, uint32_t idx) {
 // Grid-wide barrier with a bounded wait.  Workgroup 0 collects the arrival
 // flags and publishes a release word (generation << 1 | failed).  Returns
 // false if any wait timed out; every workgroup then leaves the kernel.
+//
+// Every workgroup makes its own writes visible (agent-scope release: L2
+// write-back) before raising its flag, so workgroup 0 publishes the release
+// word as soon as it has seen all flags and only then takes its own acquire
+// (L2 invalidate) for the reads that follow.  One wave per workgroup runs the
+// acquire; the workgroup barrier after it orders the other waves' reads.
 __device__ __forceinline__ bool grid_barrier(const KArgs& a, uint32_t& gen, int* s_fail, int wg,
                                              int G) {
   ++gen;
@@ -87,12 +93,12 @@ __device__ __forceinline__ bool grid_barrier(const KArgs& a, uint32_t& gen, int*
         __builtin_amdgcn_s_sleep(1);
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     __syncthreads();
     if (threadIdx.x == 0) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       __hip_atomic_store(&a.hdr->release, (target << 1) | (uint32_t)(*s_fail != 0),
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
   } else if (threadIdx.x == 0) {
     *s_fail = 0;
