@@ -267,31 +267,79 @@ __device__ __forceinline__ void dynamics_vjp(const DevProblem& P, const float* x
   }
 }
 
+// Trigonometric values of a state that every lane of the wave holds: the
+// quadrotor's three angles are evaluated on lanes 0-2 at once and broadcast
+// (one sincos on the serial chain instead of three; same values).
+__device__ __forceinline__ float lane_value(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+template <int SYS>
+__device__ __forceinline__ Trig wave_trig(const float* x, int lane) {
+  if constexpr (SYS == PAKR_QUAD) {
+    const float ang = lane == 0 ? x[3] : (lane == 1 ? x[4] : x[5]);
+    float sv, cv;
+    sincosf(ang, &sv, &cv);
+    Trig g;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      g.s[k] = lane_value(sv, k);
+      g.c[k] = lane_value(cv, k);
+    }
+    g.t = 0.0f;
+    return g;
+  } else {
+    return trig_of<SYS>(x);
+  }
+}
+
+// One RK4 step (as the planner takes it) on a state the whole wave holds.
+template <int SYS>
+__device__ __forceinline__ void rk4_step_wave(const DevProblem& P, float* x, const float* u,
+                                              float h, int lane) {
+  constexpr int D = Sys<SYS>::D;
+  float k1[D], k2[D], k3[D], k4[D], t[D];
+  const float hh = 0.5f * h;
+  dynamics_trig<SYS>(P, x, u, wave_trig<SYS>(x, lane), k1);
+#pragma unroll
+  for (int i = 0; i < D; ++i) t[i] = x[i] + hh * k1[i];
+  dynamics_trig<SYS>(P, t, u, wave_trig<SYS>(t, lane), k2);
+#pragma unroll
+  for (int i = 0; i < D; ++i) t[i] = x[i] + hh * k2[i];
+  dynamics_trig<SYS>(P, t, u, wave_trig<SYS>(t, lane), k3);
+#pragma unroll
+  for (int i = 0; i < D; ++i) t[i] = x[i] + h * k3[i];
+  dynamics_trig<SYS>(P, t, u, wave_trig<SYS>(t, lane), k4);
+  const float h6 = h * (1.0f / 6.0f);
+#pragma unroll
+  for (int i = 0; i < D; ++i) x[i] = x[i] + h6 * (k1[i] + 2.0f * (k2[i] + k3[i]) + k4[i]);
+}
+
 // Reverse of one RK4 step taken from x under control u: lam holds dJ/dx_{n+1}
 // on entry and the part of dJ/dx_n that flows through the step on exit;
 // gu accumulates dJ/du.  The four stage states are recomputed from x.
 template <int SYS>
 __device__ __forceinline__ void rk4_step_vjp(const DevProblem& P, const float* x, const float* u,
-                                             float h, float* lam, float* gu) {
+                                             float h, float* lam, float* gu, int lane) {
   constexpr int D = Sys<SYS>::D;
   float k[3][D], xs[4][D];
   Trig tg[4];
   const float hh = 0.5f * h;
 #pragma unroll
   for (int i = 0; i < D; ++i) xs[0][i] = x[i];
-  tg[0] = trig_of<SYS>(xs[0]);
+  tg[0] = wave_trig<SYS>(xs[0], lane);
   dynamics_trig<SYS>(P, xs[0], u, tg[0], k[0]);
 #pragma unroll
   for (int i = 0; i < D; ++i) xs[1][i] = x[i] + hh * k[0][i];
-  tg[1] = trig_of<SYS>(xs[1]);
+  tg[1] = wave_trig<SYS>(xs[1], lane);
   dynamics_trig<SYS>(P, xs[1], u, tg[1], k[1]);
 #pragma unroll
   for (int i = 0; i < D; ++i) xs[2][i] = x[i] + hh * k[1][i];
-  tg[2] = trig_of<SYS>(xs[2]);
+  tg[2] = wave_trig<SYS>(xs[2], lane);
   dynamics_trig<SYS>(P, xs[2], u, tg[2], k[2]);
 #pragma unroll
   for (int i = 0; i < D; ++i) xs[3][i] = x[i] + h * k[2][i];
-  tg[3] = trig_of<SYS>(xs[3]);
+  tg[3] = wave_trig<SYS>(xs[3], lane);
   // x_{n+1} = x + h/6 (k1 + 2 k2 + 2 k3 + k4); stage s (0-based) evaluates f
   // at x + c_s k_{s-1} with c = (h/2, h/2, h)
   const float h6 = h * (1.0f / 6.0f);
@@ -356,7 +404,7 @@ __global__ __launch_bounds__(WAVE) void k_rollout_fwd(TrajArgs a) {
       J += a.R.w_u * edge_t * z * z;
     }
     for (int t = 0; t < P.T; ++t) {
-      rk4_step<SYS>(P, x, u, P.dt);
+      rk4_step_wave<SYS>(P, x, u, P.dt, lane);
       const size_t n = (size_t)e * P.T + t + 1;
       if (lane == 0) {
 #pragma unroll
@@ -417,7 +465,7 @@ __global__ __launch_bounds__(WAVE) void k_rollout_bwd(TrajArgs a) {
       const size_t n = (size_t)e * P.T + t;  // step n takes x_n to x_{n+1}
 #pragma unroll
       for (int c = 0; c < D; ++c) x[c] = ck[n * D + c];
-      rk4_step_vjp<SYS>(P, x, u, P.dt, lam, gu);
+      rk4_step_vjp<SYS>(P, x, u, P.dt, lam, gu, lane);
       if (n > 0) {
         float g[D];
 #pragma unroll

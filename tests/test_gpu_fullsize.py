@@ -73,3 +73,33 @@ def test_sampled_parity_on_large_trees(cfg, target, chunk):
                 assert rel_err(tr["xnew"][j], xT).max() <= 1e-4
                 assert rel_err(tr["cnew"][j], c).max() <= 1e-4
     plan.close()
+
+
+def test_batched_form_at_bench_size_equals_single_query_plans():
+    """The 256-query mixed batch in bench.py's launch configuration (tuned B and A per
+    system, automatic team sizes, tuned lanes per system): sampled queries must end in
+    the same state as planning them alone."""
+    from paper_2607_03987_amd import autotune
+
+    tuned = autotune.load_table()
+    probs = [p.replace(max_iters_per_round=50)
+             for p in W.config_c5(n_queries=256, seed=0, settings=autotune.batch_settings(tuned))]
+    lanes = autotune.batch_lanes(tuned)
+    print("case batch of 256 mixed queries, 2 rounds, auto teams", flush=True)
+    bp = pakr.BatchPlan(probs, lanes=[lanes.get(p.system, 1) for p in probs])
+    bp.replan(max_rounds=2)
+    teams = [bp.team(q) for q in range(len(probs))]
+    assert max(teams) > 1 and min(teams) >= 1
+    rng = np.random.default_rng(3)
+    sample = sorted(set(rng.choice(len(probs), 10, replace=False).tolist()) |
+                    {int(np.argmax(teams))})
+    for q in sample:
+        single = pakr.Plan(probs[q], lanes=lanes.get(probs[q].system, 1))
+        single.replan(max_rounds=2)
+        sb, ss = bp.status(q), single.status()
+        for key in ("total_iters", "expansions", "insertions", "n_nodes", "n_solutions"):
+            assert sb[key] == ss[key], (q, teams[q], key, sb[key], ss[key])
+        assert [(s["round"], s["iter"], s["node"], s["cost"]) for s in bp.solutions(q)] == \
+               [(s["round"], s["iter"], s["node"], s["cost"]) for s in single.solutions()], q
+        single.close()
+    bp.close()
