@@ -112,6 +112,8 @@ def batched_vs_plain(torch, pakr, W, n_queries, rounds, iters_per_round, lanes=N
     batch_wall = time.perf_counter() - t0
     batch_ms = e0.elapsed_time(e1)
     bst = [bp.status(q) for q in range(len(probs))]
+    batch_flops = sum(s["expansions"] * flops_per_expansion(p) + s["nn_pairs"] * nn_flops_per_pair(p)
+                      for s, p in zip(bst, probs))
     b_sols = [bp.solutions(q) for q in range(len(probs))]
     t_base = min(s["clock_start_ms"] for s in bst)
     b_done = [s["clock_end_ms"] - t_base for s in bst]
@@ -148,7 +150,12 @@ def batched_vs_plain(torch, pakr, W, n_queries, rounds, iters_per_round, lanes=N
                     "wall_ms": batch_wall * 1e3, "grid": bst[0]["grid"],
                     "p50_done_ms": pct(b_done, 50), "p99_done_ms": pct(b_done, 99),
                     "p50_first_ms": pct(b_first, 50), "p99_first_ms": pct(b_first, 99),
-                    "expansions": sum(s["expansions"] for s in bst)},
+                    "expansions": sum(s["expansions"] for s in bst),
+                    "roofline": {"bound": "alu", "kernel": "k_batch",
+                                 "achieved": batch_flops / (batch_ms / 1e3) / 1e12,
+                                 "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                 "frac": batch_flops / (batch_ms / 1e3) / 1e12 /
+                                 FP32_VECTOR_PEAK_TFLOPS}},
         "plain": {"queries_per_s": n_queries / (sum(p_ms) / 1e3), "total_ms": sum(p_ms),
                   "wall_ms": plain_wall * 1e3,
                   "p50_alone_ms": pct(p_ms, 50), "p99_alone_ms": pct(p_ms, 99),
@@ -174,10 +181,18 @@ def refinement_leg(torch, pakr, refine, W, budget_ms, n_multi):
     plan = pakr.Plan(prob)
     plan.replan(budget_ms=budget_ms)
     st = plan.status()
+    c4_flops = st["expansions"] * flops_per_expansion(prob) + st["nn_pairs"] * nn_flops_per_pair(prob)
     out = {"workload": "12D quadrotor AO-x, [0,10]^3, 50 spheres r U(0.3,1.2), B 8192, A 16, "
                        f"T 40, dt 0.02, tree capacity 2^20, {budget_ms:.0f} ms, then 50 adjoint "
                        "steps on the best path",
-           "solved": st["n_solutions"] > 0, "c_best": st["c_best"]}
+           "solved": st["n_solutions"] > 0, "c_best": st["c_best"],
+           "planner": {"expansions_per_s": st["expansions"] / (st["call_ms"] / 1e3),
+                       "time_to_first_ms": st["t_first_ms"], "grid": st["grid"],
+                       "roofline": {"bound": "alu", "kernel": "k_plan<QUAD>",
+                                    "achieved": c4_flops / (st["call_ms"] / 1e3) / 1e12,
+                                    "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                    "frac": c4_flops / (st["call_ms"] / 1e3) / 1e12 /
+                                    FP32_VECTOR_PEAK_TFLOPS}}}
     if st["n_solutions"] == 0:
         plan.close()
         return out

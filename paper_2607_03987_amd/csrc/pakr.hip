@@ -63,10 +63,27 @@ int lanes_for(const pakr_params& p, int n_obs, int grid_limit) {
   return L;
 }
 
-Layout make_layout(int d, int m, const pakr_params& p, int G, int obs_floats, int lanes) {
+// Rollout threads per workgroup.  A candidate's rollout is one serial chain
+// per lane; when that chain is long (car, quadrotor: trigonometry in every
+// evaluation of f) half the workgroup takes candidates, so each SIMD runs one
+// rollout wave instead of two, provided that still leaves at most one rollout
+// chunk per workgroup.  Short chains (double integrators) use the whole
+// workgroup: more rollout workgroups would cost more in the insertion scan and
+// the barrier than the shorter chain saves.
+int rollout_threads(const pakr_system& sys, const pakr_params& p, int n_obs, int lanes, int G) {
+  const double f_eval = sys.id == PAKR_QUAD ? 204.0 : (sys.id == PAKR_CAR ? 128.0 : 0.0);
+  const double chain =
+      (double)p.T * (12.0 * sys.d + 4.0 * f_eval + 3.0 * sys_npos(sys.id) * n_obs / lanes);
+  const long long half = NT / 2;
+  const bool fits = ((long long)p.B * lanes + half - 1) / half <= G;
+  return (chain >= 8000.0 && fits) ? (int)half : NT;
+}
+
+Layout make_layout(int d, int m, const pakr_params& p, int G, int obs_floats, int lanes,
+                   int rt = NT) {
   Layout L{};
   const int K = p.B / p.A;
-  const int cpb = NT / lanes;
+  const int cpb = rt / lanes;
   const int GR = (p.B + cpb - 1) / cpb;
   const size_t S = (size_t)GR * cpb;
   const int maxe = p.max_path_edges > 0 ? p.max_path_edges : DEFAULT_PATH_EDGES;
@@ -243,7 +260,7 @@ int qt_for(int K) { return K <= NT ? 1 : (K <= 2 * NT ? 2 : 4); }
 
 // The device record of one query planned by G workgroups with L lanes per candidate.
 DevProblem make_problem(const pakr_system& sys, const pakr_scene& scene, const pakr_goal& goal,
-                        const pakr_params& prm, int G, int lanes) {
+                        const pakr_params& prm, int G, int lanes, int rt = NT) {
   DevProblem Q;
   std::memset(&Q, 0, sizeof Q);
   const int P = scene.npos;
@@ -263,7 +280,7 @@ DevProblem make_problem(const pakr_system& sys, const pakr_scene& scene, const p
   Q.n_sph = scene.n_sphere;
   Q.G = G;
   Q.lanes = lanes;
-  Q.cpb = NT / lanes;
+  Q.cpb = rt / lanes;
   Q.G_roll = (prm.B + Q.cpb - 1) / Q.cpb;
   Q.max_path_edges = prm.max_path_edges > 0 ? prm.max_path_edges : DEFAULT_PATH_EDGES;
   Q.obs_floats = obs_floats_of(P, scene.n_box, scene.n_sphere);
@@ -281,6 +298,10 @@ DevProblem make_problem(const pakr_system& sys, const pakr_scene& scene, const p
     Q.edge_duration = ed;
   }
   for (int i = 0; i < 8; ++i) Q.dyn[i] = sys.dyn[i];
+  if (sys.id == PAKR_QUAD) {
+    // reciprocal inertias (the kernels multiply instead of dividing)
+    for (int c = 0; c < 3; ++c) Q.dyn[5 + c] = 1.0f / sys.dyn[2 + c];
+  }
   for (int i = 0; i < PAKR_MAX_D; ++i) {
     Q.sample_lo[i] = sys.sample_lo[i];
     Q.sample_hi[i] = sys.sample_hi[i];
@@ -461,6 +482,7 @@ hipError_t read_path(const KArgs& a, int ne, float* states, float* actions) {
 struct pakr_plan {
   KArgs args;          // buffers and problem record; limits set per call
   int G = 0, qt = 1;
+  int rt = NT;         // rollout threads per workgroup
   hipStream_t stream = nullptr;
   double ticks_per_ms = 100000.0;
   void* ws = nullptr;
@@ -528,9 +550,10 @@ size_t pakr_workspace_size(const pakr_system* sys, const pakr_params* params,
   const int G = params->grid > 0 ? params->grid : AUTO_GRID_MAX;
   const int nb = std::max(scene->n_box, 0), ns = std::max(scene->n_sphere, 0);
   const int of = obs_floats_of(sys_npos(sys->id), nb, ns);
-  size_t worst = 0;  // the lane choice depends on the device; size for the largest layout
-  for (int lanes = 1; lanes <= 8; lanes <<= 1)
-    worst = std::max(worst, make_layout(d, m, *params, G, of, lanes).total);
+  size_t worst = 0;  // the lane and rollout-thread choices depend on the device:
+  for (int lanes = 1; lanes <= 16; lanes <<= 1)  // size for the largest layout
+    for (int rt = NT / 2; rt <= NT; rt *= 2)
+      worst = std::max(worst, make_layout(d, m, *params, G, of, lanes, rt).total);
   return worst;
 }
 
@@ -598,7 +621,8 @@ int pakr_plan_init(const pakr_system* sys, const pakr_scene* scene, const float*
     return fail(nullptr, PAKR_E_INVALID_ARG, buf);
   }
   pl->G = G;
-  pl->L = make_layout(sys->d, sys->m, *params, G, of, lanes);
+  pl->rt = rollout_threads(*sys, *params, scene->n_box + scene->n_sphere, lanes, G);
+  pl->L = make_layout(sys->d, sys->m, *params, G, of, lanes, pl->rt);
   const size_t need = pl->L.total;
   if (d_workspace) {
     if (ws_bytes < need) {
@@ -619,7 +643,7 @@ int pakr_plan_init(const pakr_system* sys, const pakr_scene* scene, const float*
     }
     pl->own_ws = true;
   }
-  const DevProblem Q = make_problem(*sys, *scene, *goal, *params, G, lanes);
+  const DevProblem Q = make_problem(*sys, *scene, *goal, *params, G, lanes, pl->rt);
   pl->args = make_args(Q, static_cast<char*>(pl->ws), pl->L);
   e = upload_query(pl->args, pack_obstacles(*scene), x_init, G, pl->stream);
   if (e != hipSuccess) {

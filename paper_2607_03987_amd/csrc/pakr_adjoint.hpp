@@ -217,6 +217,7 @@ __device__ __forceinline__ void dynamics_vjp(const DevProblem& P, const float* x
   } else {
     const float inv_m = 1.0f / P.dyn[0], g = P.dyn[1];
     const float Ix = P.dyn[2], Iy = P.dyn[3], Iz = P.dyn[4];
+    const float iIx = P.dyn[5], iIy = P.dyn[6], iIz = P.dyn[7];  // 1 / inertia
     const float sph = tg.s[0], cph = tg.c[0], sth = tg.s[1], cth = tg.c[1];
     const float sps = tg.s[2], cps = tg.c[2];
     const float v0 = x[6], v1 = x[7], v2 = x[8];
@@ -240,7 +241,7 @@ __device__ __forceinline__ void dynamics_vjp(const DevProblem& P, const float* x
     const float Rv0 = r00 * v0 + r01 * v1 + r02 * v2, Rv1 = r10 * v0 + r11 * v1 + r12 * v2;
     gx[5] += -wp0 * Rv1 + wp1 * Rv0;
     // Euler-angle rates
-    const float tth = sth / cth, ict = 1.0f / cth;
+    const float ict = 1.0f / cth, tth = sth * ict;
     const float a = q * sph + r * cph, bq = q * cph - r * sph;
     gx[9] += wf;
     gx[10] += wf * sph * tth + wt * cph + ws * sph * ict;
@@ -258,12 +259,12 @@ __device__ __forceinline__ void dynamics_vjp(const DevProblem& P, const float* x
     gx[4] += g * (W0 * cth + W1 * sth * sph + W2 * sth * cph);
     gu[0] += W2 * inv_m;
     // body rates' = I^-1 (tau - w x I w)
-    gu[1] += Z0 / Ix;
-    gu[2] += Z1 / Iy;
-    gu[3] += Z2 / Iz;
-    gx[9] += -Z1 * (Ix - Iz) * r / Iy - Z2 * (Iy - Ix) * q / Iz;
-    gx[10] += -Z0 * (Iz - Iy) * r / Ix - Z2 * (Iy - Ix) * p / Iz;
-    gx[11] += -Z0 * (Iz - Iy) * q / Ix - Z1 * (Ix - Iz) * p / Iy;
+    gu[1] += Z0 * iIx;
+    gu[2] += Z1 * iIy;
+    gu[3] += Z2 * iIz;
+    gx[9] += -Z1 * (Ix - Iz) * r * iIy - Z2 * (Iy - Ix) * q * iIz;
+    gx[10] += -Z0 * (Iz - Iy) * r * iIx - Z2 * (Iy - Ix) * p * iIz;
+    gx[11] += -Z0 * (Iz - Iy) * q * iIx - Z1 * (Ix - Iz) * p * iIy;
   }
 }
 

@@ -180,6 +180,7 @@ __device__ __forceinline__ void dynamics_trig(const DevProblem& P, const float* 
     // quadrotor, Z-Y-X Euler angles; body-frame velocity (ub,vb,wb), rates (p,q,r)
     const float inv_m = 1.0f / P.dyn[0], g = P.dyn[1];
     const float Ix = P.dyn[2], Iy = P.dyn[3], Iz = P.dyn[4];
+    const float iIx = P.dyn[5], iIy = P.dyn[6], iIz = P.dyn[7];  // 1 / inertia
     const float sph = tg.s[0], cph = tg.c[0], sth = tg.s[1], cth = tg.c[1];
     const float sps = tg.s[2], cps = tg.c[2];
     const float ub = x[6], vb = x[7], wb = x[8];
@@ -201,9 +202,9 @@ __device__ __forceinline__ void dynamics_trig(const DevProblem& P, const float* 
     xd[7] = -(r * ub - p * wb) - g * r21;
     xd[8] = -(p * vb - q * ub) - g * r22 + u[0] * inv_m;
     // w' = I^-1 (tau - w x I w)
-    xd[9] = (u[1] - (Iz - Iy) * q * r) / Ix;
-    xd[10] = (u[2] - (Ix - Iz) * r * p) / Iy;
-    xd[11] = (u[3] - (Iy - Ix) * p * q) / Iz;
+    xd[9] = (u[1] - (Iz - Iy) * q * r) * iIx;
+    xd[10] = (u[2] - (Ix - Iz) * r * p) * iIy;
+    xd[11] = (u[3] - (Iy - Ix) * p * q) * iIz;
   }
 }
 

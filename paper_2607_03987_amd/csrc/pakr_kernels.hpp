@@ -419,9 +419,11 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
 
       // L consecutive lanes share candidate j: each integrates the edge and
       // tests every L-th obstacle; the group ORs its hits
+      // (only the first L * CPB threads take candidates: with half the
+      // workgroup, each SIMD runs one rollout wave)
       const int lg = tid % L;
       const int j = j0 + tid / L;
-      const bool active = j < B;
+      const bool active = tid < L * CPB && j < B;
       float x[D], u[M];
       float cost = 0.0f;
       bool valid = false, prune_ok = false, in_goal = false;
