@@ -241,7 +241,7 @@ __device__ __forceinline__ void dynamics_vjp(const DevProblem& P, const float* x
     const float Rv0 = r00 * v0 + r01 * v1 + r02 * v2, Rv1 = r10 * v0 + r11 * v1 + r12 * v2;
     gx[5] += -wp0 * Rv1 + wp1 * Rv0;
     // Euler-angle rates
-    const float ict = 1.0f / cth, tth = sth * ict;
+    const float ict = __builtin_amdgcn_rcpf(cth), tth = sth * ict;  // as in f
     const float a = q * sph + r * cph, bq = q * cph - r * sph;
     gx[9] += wf;
     gx[10] += wf * sph * tth + wt * cph + ws * sph * ict;

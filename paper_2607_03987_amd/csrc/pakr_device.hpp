@@ -192,7 +192,7 @@ __device__ __forceinline__ void dynamics_trig(const DevProblem& P, const float* 
     xd[0] = r00 * ub + r01 * vb + r02 * wb;
     xd[1] = r10 * ub + r11 * vb + r12 * wb;
     xd[2] = r20 * ub + r21 * vb + r22 * wb;
-    const float inv_cth = 1.0f / cth;
+    const float inv_cth = __builtin_amdgcn_rcpf(cth);  // hardware reciprocal, 1 ulp
     const float qs_rc = q * sph + r * cph;
     xd[3] = p + qs_rc * sth * inv_cth;
     xd[4] = q * cph - r * sph;
