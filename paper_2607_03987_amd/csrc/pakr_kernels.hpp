@@ -61,13 +61,13 @@ __device__ __forceinline__ unsigned long long pack_key(float v, uint32_t idx) {
   return ((unsigned long long)__float_as_uint(v) << 32) | (unsigned long long)idx;
 }
 
-// Grid-wide barrier with a bounded wait.  Workgroup 0 collects the arrival
-// flags and publishes a release word (generation << 1 | failed).  Returns
+// Grid-wide barrier with a bounded wait.  The last workgroup collects the
+// arrival flags and publishes a release word (generation << 1 | failed).  Returns
 // false if any wait timed out; every workgroup then leaves the kernel.
 //
 // Every workgroup makes its own writes visible (agent-scope release: L2
-// write-back) before raising its flag, so workgroup 0 publishes the release
-// word as soon as it has seen all flags and only then takes its own acquire
+// write-back) before raising its flag, so the collecting workgroup publishes
+// the release word as soon as it has seen all flags and only then takes its own acquire
 // (L2 invalidate) for the reads that follow.  One wave per workgroup runs the
 // acquire; the workgroup barrier after it orders the other waves' reads.
 __device__ __forceinline__ bool grid_barrier(const KArgs& a, uint32_t& gen, int* s_fail, int wg,
@@ -76,10 +76,11 @@ __device__ __forceinline__ bool grid_barrier(const KArgs& a, uint32_t& gen, int*
   __syncthreads();
   if (G == 1) return true;
   const uint32_t target = gen & 0x7fffffffu;
-  if (wg == 0) {
+  const int master = G - 1;  // owns no more NN tiles than any other workgroup
+  if (wg == master) {
     if (threadIdx.x == 0) *s_fail = 0;
     __syncthreads();
-    for (int i = threadIdx.x + 1; i < G; i += NT) {
+    for (int i = threadIdx.x; i < master; i += NT) {
       long long limit = 0;
       while (__hip_atomic_load(&a.bar_flags[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) !=
              target) {
