@@ -167,12 +167,45 @@ static void f_quad(const orc_problem* p, const double* x, const double* u, doubl
   xd[11] = (u[3] - wxIw[2]) / Iz;
 }
 
+/* Dubins airplane (Sec. V-B): state (x, y, z, yaw, pitch, speed), controls
+ * (yaw rate, pitch rate, acceleration); the speed acts along the heading
+ * given by yaw and pitch. */
+static void f_dubins(const double* x, const double* u, double* xd) {
+  double ps = x[3], th = x[4], v = x[5];
+  xd[0] = v * cos(ps) * cos(th);
+  xd[1] = v * sin(ps) * cos(th);
+  xd[2] = v * sin(th);
+  xd[3] = u[0];
+  xd[4] = u[1];
+  xd[5] = u[2];
+}
+
+/* Unicycle 1 (Sec. V-C): state (x, y, heading), controls (speed, turn rate). */
+static void f_uni1(const double* x, const double* u, double* xd) {
+  xd[0] = u[0] * cos(x[2]);
+  xd[1] = u[0] * sin(x[2]);
+  xd[2] = u[1];
+}
+
+/* Unicycle 2 (Sec. V-C): state (x, y, heading, speed, turn rate), controls
+ * (acceleration, angular acceleration). */
+static void f_uni2(const double* x, const double* u, double* xd) {
+  xd[0] = x[3] * cos(x[2]);
+  xd[1] = x[3] * sin(x[2]);
+  xd[2] = x[4];
+  xd[3] = u[0];
+  xd[4] = u[1];
+}
+
 void orc_dynamics(const orc_problem* p, const double* x, const double* u, double* xd) {
   switch (p->system) {
     case ORC_DI2: f_double_integrator(2, x, u, xd); break;
     case ORC_DI3: f_double_integrator(3, x, u, xd); break;
     case ORC_CAR: f_car(p, x, u, xd); break;
     case ORC_QUAD: f_quad(p, x, u, xd); break;
+    case ORC_DUBINS: f_dubins(x, u, xd); break;
+    case ORC_UNI1: f_uni1(x, u, xd); break;
+    case ORC_UNI2: f_uni2(x, u, xd); break;
     default: for (int i = 0; i < p->d; ++i) xd[i] = NAN;
   }
 }
@@ -816,6 +849,23 @@ static void c_dynamics(const orc_problem* p, const cplx* x, const cplx* u, cplx*
     xd[0] = x[3] * ccos(x[2]);
     xd[1] = x[3] * csin(x[2]);
     xd[2] = x[3] * ctan(x[4]) / L;
+    xd[3] = u[0];
+    xd[4] = u[1];
+  } else if (p->system == ORC_DUBINS) {
+    xd[0] = x[5] * ccos(x[3]) * ccos(x[4]);
+    xd[1] = x[5] * csin(x[3]) * ccos(x[4]);
+    xd[2] = x[5] * csin(x[4]);
+    xd[3] = u[0];
+    xd[4] = u[1];
+    xd[5] = u[2];
+  } else if (p->system == ORC_UNI1) {
+    xd[0] = u[0] * ccos(x[2]);
+    xd[1] = u[0] * csin(x[2]);
+    xd[2] = u[1];
+  } else if (p->system == ORC_UNI2) {
+    xd[0] = x[3] * ccos(x[2]);
+    xd[1] = x[3] * csin(x[2]);
+    xd[2] = x[4];
     xd[3] = u[0];
     xd[4] = u[1];
   } else {

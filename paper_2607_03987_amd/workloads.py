@@ -22,8 +22,9 @@ from typing import List, Optional
 import numpy as np
 
 # System identifiers shared by the C ABI (include/pakr.h) and the reference.
-DI2, DI3, CAR, QUAD = 0, 1, 2, 3
-SYSTEM_NAMES = {DI2: "di2", DI3: "di3", CAR: "car", QUAD: "quad"}
+DI2, DI3, CAR, QUAD, DUBINS, UNI1, UNI2 = 0, 1, 2, 3, 4, 5, 6
+SYSTEM_NAMES = {DI2: "di2", DI3: "di3", CAR: "car", QUAD: "quad", DUBINS: "dubins",
+                UNI1: "uni1", UNI2: "uni2"}
 
 # Cost kinds (problem statement, Sec. III: path length or time optimality).
 COST_DURATION, COST_PATH_LENGTH = 0, 1
@@ -132,6 +133,33 @@ def system_table(system: int, ws_lo, ws_hi) -> dict:
                     u_lo=[0.0, -0.1, -0.1, -0.1], u_hi=[thrust_max, 0.1, 0.1, 0.1],
                     lim_lo=lim_lo, lim_hi=lim_hi, vnorm_max=0.0,
                     h_speed=float(np.float32(math.sqrt(3.0) * vel)))
+    if system == DUBINS:
+        # Dubins airplane: state (x,y,z, yaw, pitch, speed); control (yaw rate,
+        # pitch rate, acceleration); pitch within +-0.6, speed in [0.5, 2]
+        d, m = 6, 3
+        s_lo = [ws_lo[0], ws_lo[1], ws_lo[2], -pi, -0.6, 0.5]
+        s_hi = [ws_hi[0], ws_hi[1], ws_hi[2], pi, 0.6, 2.0]
+        lim_lo = [-inf, -inf, -inf, -inf, -0.6, 0.5]
+        lim_hi = [inf, inf, inf, inf, 0.6, 2.0]
+        return dict(d=d, m=m, npos=3, dyn=np.zeros(8), sample_lo=s_lo, sample_hi=s_hi,
+                    u_lo=[-1.0, -0.5, -0.5], u_hi=[1.0, 0.5, 0.5], lim_lo=lim_lo,
+                    lim_hi=lim_hi, vnorm_max=0.0, h_speed=2.0)
+    if system == UNI1:
+        # unicycle 1: state (x, y, heading); control (speed, turn rate)
+        s_lo = [ws_lo[0], ws_lo[1], -pi]
+        s_hi = [ws_hi[0], ws_hi[1], pi]
+        return dict(d=3, m=2, npos=2, dyn=np.zeros(8), sample_lo=s_lo, sample_hi=s_hi,
+                    u_lo=[-0.5, -0.5], u_hi=[0.5, 0.5], lim_lo=[-inf] * 3, lim_hi=[inf] * 3,
+                    vnorm_max=0.0, h_speed=0.5)
+    if system == UNI2:
+        # unicycle 2: state (x, y, heading, speed, turn rate); control
+        # (acceleration, angular acceleration); |speed|, |turn rate| <= 0.5
+        s_lo = [ws_lo[0], ws_lo[1], -pi, -0.5, -0.5]
+        s_hi = [ws_hi[0], ws_hi[1], pi, 0.5, 0.5]
+        return dict(d=5, m=2, npos=2, dyn=np.zeros(8), sample_lo=s_lo, sample_hi=s_hi,
+                    u_lo=[-0.25, -0.25], u_hi=[0.25, 0.25],
+                    lim_lo=[-inf, -inf, -inf, -0.5, -0.5], lim_hi=[inf, inf, inf, 0.5, 0.5],
+                    vnorm_max=0.0, h_speed=0.5)
     raise ValueError(f"unknown system {system}")
 
 
@@ -146,11 +174,11 @@ def _clear_of(kind: str, c, h_or_r, p, clearance: float) -> bool:
 
 
 def make_scene(rng: np.random.Generator, ws_lo, ws_hi, n_box: int, box_side, n_sph: int,
-               sph_r, start_pos, goal_c, goal_r: float):
+               sph_r, start_pos, goal_c, goal_r: float, square: bool = False):
     """Random axis-aligned boxes and spheres, redrawn while too close to start or goal.
 
     A box (sphere) is redrawn if it comes within 0.5 of the start position or
-    within goal_r + 0.5 of the goal centre.
+    within goal_r + 0.5 of the goal centre.  square: boxes with equal sides.
     """
     ws_lo = np.asarray(ws_lo, np.float64)
     ws_hi = np.asarray(ws_hi, np.float64)
@@ -158,7 +186,8 @@ def make_scene(rng: np.random.Generator, ws_lo, ws_hi, n_box: int, box_side, n_s
     boxes_c, boxes_h, sph_cs, sph_rs = [], [], [], []
     for _ in range(n_box):
         while True:
-            side = rng.uniform(box_side[0], box_side[1], size=D)
+            side = (np.full(D, rng.uniform(box_side[0], box_side[1])) if square
+                    else rng.uniform(box_side[0], box_side[1], size=D))
             c = rng.uniform(ws_lo, ws_hi)
             h = 0.5 * side
             if (_clear_of("box", c, h, start_pos, 0.5)
@@ -255,6 +284,52 @@ def config_c4(seed: int = 0, **over) -> Problem:
 
 
 CONFIGS = {"c1": config_c1, "c2": config_c2, "c3": config_c3, "c4": config_c4}
+
+
+# ----------------------------------------------------------------------------
+# The paper's other analytic systems (Sec. V-B, V-C) on scenes of the same kind.
+# ----------------------------------------------------------------------------
+
+def config_dubins(seed: int = 0, **over) -> Problem:
+    """Dubins airplane, [0,10]^3, 30 boxes side U(0.5,2.5); B 4096, A 8, T 20, dt .05."""
+    rng = np.random.default_rng([seed, 6])
+    start = [1.0, 1.0, 1.0, 0.0, 0.0, 1.0]
+    goal_c, goal_r = [9.0, 9.0, 9.0], 1.0
+    scene = make_scene(rng, [0, 0, 0], [10, 10, 10], 30, (0.5, 2.5), 0, (0, 0), start[:3],
+                       goal_c, goal_r)
+    kw = dict(B=4096, A=8, T=20, dt=np.float32(0.05), n_cap=262144, cost_kind=COST_DURATION,
+              seed=seed, name="dubins")
+    kw.update(over)
+    return build_problem(DUBINS, [0, 0, 0], [10, 10, 10], *scene, start, goal_c, goal_r, **kw)
+
+
+def config_uni1(seed: int = 0, **over) -> Problem:
+    """Unicycle 1, [0,10]^2, 40 square obstacles side U(0.5,1.2); B 1024, A 8, T 10, dt .1."""
+    rng = np.random.default_rng([seed, 7])
+    start = [1.0, 1.0, 0.0]
+    goal_c, goal_r = [9.0, 9.0], 0.5
+    scene = make_scene(rng, [0, 0], [10, 10], 40, (0.5, 1.2), 0, (0, 0), start[:2], goal_c,
+                       goal_r, square=True)
+    kw = dict(B=1024, A=8, T=10, dt=np.float32(0.1), n_cap=131072, cost_kind=COST_DURATION,
+              seed=seed, name="uni1")
+    kw.update(over)
+    return build_problem(UNI1, [0, 0], [10, 10], *scene, start, goal_c, goal_r, **kw)
+
+
+def config_uni2(seed: int = 0, **over) -> Problem:
+    """Unicycle 2, [0,10]^2, 40 square obstacles side U(0.5,1.2); B 1024, A 8, T 10, dt .1."""
+    rng = np.random.default_rng([seed, 8])
+    start = [1.0, 1.0, 0.0, 0.0, 0.0]
+    goal_c, goal_r = [9.0, 9.0], 0.5
+    scene = make_scene(rng, [0, 0], [10, 10], 40, (0.5, 1.2), 0, (0, 0), start[:2], goal_c,
+                       goal_r, square=True)
+    kw = dict(B=1024, A=8, T=10, dt=np.float32(0.1), n_cap=131072, cost_kind=COST_DURATION,
+              seed=seed, name="uni2")
+    kw.update(over)
+    return build_problem(UNI2, [0, 0], [10, 10], *scene, start, goal_c, goal_r, **kw)
+
+
+MORE_CONFIGS = {"dubins": config_dubins, "uni1": config_uni1, "uni2": config_uni2}
 
 # Per-system planner settings used for the mixed batch.
 _BATCH_SETTINGS = {
