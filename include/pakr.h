@@ -56,8 +56,14 @@ enum pakr_system_id {
   PAKR_DI2 = 0,  /* 2D double integrator: x=(px,py,vx,vy), u=(ax,ay)        */
   PAKR_DI3 = 1,  /* 3D double integrator: x=(p, v) in R^6, u=a in R^3       */
   PAKR_CAR = 2,  /* car: x=(px,py,theta,v,phi), u=(accel, steering rate)     */
-  PAKR_QUAD = 3  /* quadrotor: x=(p, roll,pitch,yaw, body vel, body rates),
+  PAKR_QUAD = 3, /* quadrotor: x=(p, roll,pitch,yaw, body vel, body rates),
                     u=(thrust, tau_x, tau_y, tau_z)                          */
+  PAKR_DUBINS = 4, /* Dubins airplane (Sec. V-B): x=(p in R^3, yaw, pitch,
+                      speed), u=(yaw rate, pitch rate, acceleration)         */
+  PAKR_UNI1 = 5, /* unicycle 1 (Sec. V-C): x=(px,py,heading),
+                    u=(speed, turn rate)                                     */
+  PAKR_UNI2 = 6  /* unicycle 2 (Sec. V-C): x=(px,py,heading,speed,turn rate),
+                    u=(acceleration, angular acceleration)                   */
 };
 
 /* Cost J (Sec. III): trajectory duration or path length of the positions. */

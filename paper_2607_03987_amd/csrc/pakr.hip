@@ -28,13 +28,18 @@ struct Layout {
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
-int sys_npos(int id) { return (id == PAKR_DI2 || id == PAKR_CAR) ? 2 : 3; }
+int sys_npos(int id) {
+  return (id == PAKR_DI2 || id == PAKR_CAR || id == PAKR_UNI1 || id == PAKR_UNI2) ? 2 : 3;
+}
 int sys_d(int id) {
   switch (id) {
     case PAKR_DI2: return 4;
     case PAKR_DI3: return 6;
     case PAKR_CAR: return 5;
     case PAKR_QUAD: return 12;
+    case PAKR_DUBINS: return 6;
+    case PAKR_UNI1: return 3;
+    case PAKR_UNI2: return 5;
   }
   return -1;
 }
@@ -44,8 +49,26 @@ int sys_m(int id) {
     case PAKR_DI3: return 3;
     case PAKR_CAR: return 2;
     case PAKR_QUAD: return 4;
+    case PAKR_DUBINS: return 3;
+    case PAKR_UNI1: return 2;
+    case PAKR_UNI2: return 2;
   }
   return -1;
+}
+
+// Estimated instructions of one evaluation of f beyond its linear part: the
+// transcendental functions dominate (three sincos and a reciprocal for the
+// quadrotor, a sincos and a tangent for the car, one or two sincos for the
+// Dubins airplane and the unicycles).
+double f_eval_of(int id) {
+  switch (id) {
+    case PAKR_QUAD: return 204.0;
+    case PAKR_CAR: return 128.0;
+    case PAKR_DUBINS: return 120.0;
+    case PAKR_UNI1:
+    case PAKR_UNI2: return 64.0;
+  }
+  return 0.0;
 }
 
 int obs_floats_of(int npos, int n_box, int n_sph) { return n_box * 2 * npos + n_sph * (npos + 1); }
@@ -71,7 +94,7 @@ int lanes_for(const pakr_params& p, int n_obs, int grid_limit) {
 // workgroup: more rollout workgroups would cost more in the insertion scan and
 // the barrier than the shorter chain saves.
 int rollout_threads(const pakr_system& sys, const pakr_params& p, int n_obs, int lanes, int G) {
-  const double f_eval = sys.id == PAKR_QUAD ? 204.0 : (sys.id == PAKR_CAR ? 128.0 : 0.0);
+  const double f_eval = f_eval_of(sys.id);
   const double chain =
       (double)p.T * (12.0 * sys.d + 4.0 * f_eval + 3.0 * sys_npos(sys.id) * n_obs / lanes);
   const long long half = NT / 2;
@@ -147,7 +170,7 @@ bool host_state_ok(const pakr_system& s, const pakr_scene& sc, const float* x) {
 
 // System record checks (and the scene's position dimension).
 std::string validate_system(const pakr_system* s, const pakr_scene* sc) {
-  if (s->id < PAKR_DI2 || s->id > PAKR_QUAD) return "unknown system id";
+  if (s->id < PAKR_DI2 || s->id > PAKR_UNI2) return "unknown system id";
   if (s->d != sys_d(s->id) || s->m != sys_m(s->id)) return "d/m do not match the system";
   if (sc->npos != sys_npos(s->id)) return "scene npos does not match the system";
   for (int i = 0; i < s->d; ++i) {
@@ -252,6 +275,9 @@ const void* kernel_for(int sys, int qt) {
     case PAKR_DI2: return pick_kernel<PAKR_DI2>(qt);
     case PAKR_DI3: return pick_kernel<PAKR_DI3>(qt);
     case PAKR_CAR: return pick_kernel<PAKR_CAR>(qt);
+    case PAKR_DUBINS: return pick_kernel<PAKR_DUBINS>(qt);
+    case PAKR_UNI1: return pick_kernel<PAKR_UNI1>(qt);
+    case PAKR_UNI2: return pick_kernel<PAKR_UNI2>(qt);
     default: return pick_kernel<PAKR_QUAD>(qt);
   }
 }
@@ -820,7 +846,7 @@ namespace {
 // what one round could insert.  Calibrated against measured iteration times
 // (quadrotor ~2.6 ms, 3D double integrator ~0.15 ms on one workgroup).
 double query_work(const DevProblem& Q) {
-  const double f_eval = Q.system == PAKR_QUAD ? 204.0 : (Q.system == PAKR_CAR ? 128.0 : 0.0);
+  const double f_eval = f_eval_of(Q.system);
   const double roll =
       (double)Q.B * Q.T * (12.0 * Q.d + 4.0 * f_eval + 3.0 * Q.npos * (Q.n_box + Q.n_sph));
   const double tree = std::min((double)Q.n_cap, 0.02 * Q.B * Q.max_iters_per_round);
@@ -1204,6 +1230,9 @@ const void* traj_kernel_for(int sys, int which) {
     case PAKR_DI2: return traj_kernel<PAKR_DI2>(which);
     case PAKR_DI3: return traj_kernel<PAKR_DI3>(which);
     case PAKR_CAR: return traj_kernel<PAKR_CAR>(which);
+    case PAKR_DUBINS: return traj_kernel<PAKR_DUBINS>(which);
+    case PAKR_UNI1: return traj_kernel<PAKR_UNI1>(which);
+    case PAKR_UNI2: return traj_kernel<PAKR_UNI2>(which);
     default: return traj_kernel<PAKR_QUAD>(which);
   }
 }

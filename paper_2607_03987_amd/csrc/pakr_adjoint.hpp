@@ -195,10 +195,11 @@ __device__ __forceinline__ void wave_penalty_grad(const DevProblem& P, const Ref
 }
 
 // Vector-Jacobian products of f (Eq. (1)): gx += (df/dx)^T w, gu += (df/du)^T w,
-// at a state whose trigonometric values are tg.
+// at a state x (trigonometric values tg) under control u.
 template <int SYS>
-__device__ __forceinline__ void dynamics_vjp(const DevProblem& P, const float* x, const Trig& tg,
-                                             const float* w, float* gx, float* gu) {
+__device__ __forceinline__ void dynamics_vjp(const DevProblem& P, const float* x, const float* u,
+                                             const Trig& tg, const float* w, float* gx,
+                                             float* gu) {
   if constexpr (SYS == PAKR_DI2 || SYS == PAKR_DI3) {
     constexpr int Dp = Sys<SYS>::P;
 #pragma unroll
@@ -214,7 +215,30 @@ __device__ __forceinline__ void dynamics_vjp(const DevProblem& P, const float* x
     gx[4] += v * (1.0f + t * t) * invL * w[2];
     gu[0] += w[3];
     gu[1] += w[4];
+  } else if constexpr (SYS == PAKR_DUBINS) {
+    const float sy = tg.s[0], cy = tg.c[0], sp = tg.s[1], cp = tg.c[1];
+    const float v = x[5];
+    const float wh = cy * w[0] + sy * w[1];  // w along the horizontal heading
+    gx[3] += v * cp * (cy * w[1] - sy * w[0]);
+    gx[4] += v * (cp * w[2] - sp * wh);
+    gx[5] += cp * wh + sp * w[2];
+    gu[0] += w[3];
+    gu[1] += w[4];
+    gu[2] += w[5];
+  } else if constexpr (SYS == PAKR_UNI1) {
+    const float s = tg.s[0], c = tg.c[0];
+    gx[2] += u[0] * (c * w[1] - s * w[0]);
+    gu[0] += c * w[0] + s * w[1];
+    gu[1] += w[2];
+  } else if constexpr (SYS == PAKR_UNI2) {
+    const float s = tg.s[0], c = tg.c[0];
+    gx[2] += x[3] * (c * w[1] - s * w[0]);
+    gx[3] += c * w[0] + s * w[1];
+    gx[4] += w[2];
+    gu[0] += w[3];
+    gu[1] += w[4];
   } else {
+    static_assert(SYS == PAKR_QUAD, "unknown system");
     const float inv_m = 1.0f / P.dyn[0], g = P.dyn[1];
     const float Ix = P.dyn[2], Iy = P.dyn[3], Iz = P.dyn[4];
     const float iIx = P.dyn[5], iIy = P.dyn[6], iIz = P.dyn[7];  // 1 / inertia
@@ -269,15 +293,29 @@ __device__ __forceinline__ void dynamics_vjp(const DevProblem& P, const float* x
 }
 
 // Trigonometric values of a state that every lane of the wave holds: the
-// quadrotor's three angles are evaluated on lanes 0-2 at once and broadcast
-// (one sincos on the serial chain instead of three; same values).
+// quadrotor's three angles (the Dubins airplane's two) are evaluated on lanes
+// 0-2 (0-1) at once and broadcast (one sincos on the serial chain instead of
+// three; same values).
 __device__ __forceinline__ float lane_value(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
 template <int SYS>
 __device__ __forceinline__ Trig wave_trig(const float* x, int lane) {
-  if constexpr (SYS == PAKR_QUAD) {
+  if constexpr (SYS == PAKR_DUBINS) {
+    // yaw on lane 0, pitch on lane 1
+    const float ang = lane == 0 ? x[3] : x[4];
+    float sv, cv;
+    sincosf(ang, &sv, &cv);
+    Trig g;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      g.s[k] = lane_value(sv, k);
+      g.c[k] = lane_value(cv, k);
+    }
+    g.s[2] = g.c[2] = g.t = 0.0f;
+    return g;
+  } else if constexpr (SYS == PAKR_QUAD) {
     const float ang = lane == 0 ? x[3] : (lane == 1 ? x[4] : x[5]);
     float sv, cv;
     sincosf(ang, &sv, &cv);
@@ -360,7 +398,7 @@ __device__ __forceinline__ void rk4_step_vjp(const DevProblem& P, const float* x
       gk[i] = wk[s] * lam[i] + carry[i];
       gxs[i] = 0.0f;
     }
-    dynamics_vjp<SYS>(P, xs[s], tg[s], gk, gxs, gu);
+    dynamics_vjp<SYS>(P, xs[s], u, tg[s], gk, gxs, gu);
 #pragma unroll
     for (int i = 0; i < D; ++i) {
       carry[i] = s > 0 ? cs[s - 1] * gxs[i] : 0.0f;

@@ -130,15 +130,21 @@ __device__ __forceinline__ void sample_control(const DevProblem& P, uint32_t k, 
 // Systems.  Sizes are compile-time so every state lives in registers.
 // ---------------------------------------------------------------------------
 template <int SYS> struct Sys;
-// D state dims, M controls, P position dims, CH steps per collision sweep.
+// D state dims, M controls, P position dims, CH steps per collision sweep
+// (4 where f takes two or more sincos: a longer sweep spills in the batched
+// kernel, which holds every system's loop).
 template <> struct Sys<PAKR_DI2> { static constexpr int D = 4, M = 2, P = 2, CH = 8; };
 template <> struct Sys<PAKR_DI3> { static constexpr int D = 6, M = 3, P = 3, CH = 8; };
 template <> struct Sys<PAKR_CAR> { static constexpr int D = 5, M = 2, P = 2, CH = 8; };
 template <> struct Sys<PAKR_QUAD> { static constexpr int D = 12, M = 4, P = 3, CH = 4; };
+template <> struct Sys<PAKR_DUBINS> { static constexpr int D = 6, M = 3, P = 3, CH = 4; };
+template <> struct Sys<PAKR_UNI1> { static constexpr int D = 3, M = 2, P = 2, CH = 8; };
+template <> struct Sys<PAKR_UNI2> { static constexpr int D = 5, M = 2, P = 2, CH = 8; };
 
 // The trigonometric values f needs at one state: the car's heading sine and
 // cosine and steering tangent, the quadrotor's roll, pitch and yaw sines and
-// cosines.  Computed once per evaluation (and, in the adjoint, shared between
+// cosines, the Dubins airplane's yaw and pitch sines and cosines, the
+// unicycles' heading sine and cosine.  Computed once per evaluation (and, in the adjoint, shared between
 // an RK4 stage's evaluation of f and its vector-Jacobian product).
 struct Trig {
   float s[3], c[3], t;
@@ -153,6 +159,11 @@ __device__ __forceinline__ Trig trig_of(const float* x) {
   } else if constexpr (SYS == PAKR_QUAD) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) sincosf(x[3 + k], &g.s[k], &g.c[k]);
+  } else if constexpr (SYS == PAKR_DUBINS) {
+    sincosf(x[3], &g.s[0], &g.c[0]);
+    sincosf(x[4], &g.s[1], &g.c[1]);
+  } else if constexpr (SYS == PAKR_UNI1 || SYS == PAKR_UNI2) {
+    sincosf(x[2], &g.s[0], &g.c[0]);
   }
   return g;
 }
@@ -176,7 +187,30 @@ __device__ __forceinline__ void dynamics_trig(const DevProblem& P, const float* 
     xd[2] = v * tg.t * (1.0f / P.dyn[0]);
     xd[3] = u[0];
     xd[4] = u[1];
+  } else if constexpr (SYS == PAKR_DUBINS) {
+    // state (p, yaw, pitch, speed); the controls drive yaw, pitch and speed
+    const float v = x[5];
+    const float vc = v * tg.c[1];
+    xd[0] = vc * tg.c[0];
+    xd[1] = vc * tg.s[0];
+    xd[2] = v * tg.s[1];
+    xd[3] = u[0];
+    xd[4] = u[1];
+    xd[5] = u[2];
+  } else if constexpr (SYS == PAKR_UNI1) {
+    // state (p, heading); controls (speed, turn rate)
+    xd[0] = u[0] * tg.c[0];
+    xd[1] = u[0] * tg.s[0];
+    xd[2] = u[1];
+  } else if constexpr (SYS == PAKR_UNI2) {
+    // state (p, heading, speed, turn rate); controls accelerate both
+    xd[0] = x[3] * tg.c[0];
+    xd[1] = x[3] * tg.s[0];
+    xd[2] = x[4];
+    xd[3] = u[0];
+    xd[4] = u[1];
   } else {
+    static_assert(SYS == PAKR_QUAD, "unknown system");
     // quadrotor, Z-Y-X Euler angles; body-frame velocity (ub,vb,wb), rates (p,q,r)
     const float inv_m = 1.0f / P.dyn[0], g = P.dyn[1];
     const float Ix = P.dyn[2], Iy = P.dyn[3], Iz = P.dyn[4];

@@ -786,6 +786,9 @@ __global__ __launch_bounds__(NT) void k_batch(const KArgs* __restrict__ qs,
       case PAKR_DI2: plan_loop<PAKR_DI2, 1>(a, member, team, sm); break;
       case PAKR_DI3: plan_loop<PAKR_DI3, 1>(a, member, team, sm); break;
       case PAKR_CAR: plan_loop<PAKR_CAR, 1>(a, member, team, sm); break;
+      case PAKR_DUBINS: plan_loop<PAKR_DUBINS, 1>(a, member, team, sm); break;
+      case PAKR_UNI1: plan_loop<PAKR_UNI1, 1>(a, member, team, sm); break;
+      case PAKR_UNI2: plan_loop<PAKR_UNI2, 1>(a, member, team, sm); break;
       default: plan_loop<PAKR_QUAD, 1>(a, member, team, sm); break;
     }
   }
