@@ -265,9 +265,13 @@ std::string validate(const pakr_system* s, const pakr_scene* sc, const float* x0
 
 template <int SYS>
 const void* pick_kernel(int qt) {
-  if (qt == 1) return reinterpret_cast<const void*>(&k_plan<SYS, 1>);
-  if (qt == 2) return reinterpret_cast<const void*>(&k_plan<SYS, 2>);
-  return reinterpret_cast<const void*>(&k_plan<SYS, 4>);
+  if constexpr (Sys<SYS>::D > 6) {
+    return reinterpret_cast<const void*>(&k_plan<SYS, 1>);
+  } else {
+    if (qt == 1) return reinterpret_cast<const void*>(&k_plan<SYS, 1>);
+    if (qt == 2) return reinterpret_cast<const void*>(&k_plan<SYS, 2>);
+    return reinterpret_cast<const void*>(&k_plan<SYS, 4>);
+  }
 }
 
 const void* kernel_for(int sys, int qt) {
@@ -282,11 +286,29 @@ const void* kernel_for(int sys, int qt) {
   }
 }
 
-int qt_for(int K) { return K <= NT ? 1 : (K <= 2 * NT ? 2 : 4); }
+// Targets per thread in a single-query plan's NN scan: four (one above 6
+// state dimensions, where the loop has no registers to spare), fewer when K
+// is too small for every thread to hold that many.
+int qt_for(int K, int d) {
+  int qt = d <= 6 ? 4 : 1;
+  while (qt > 1 && K <= (NT / 16) * qt / 2) qt >>= 1;
+  return qt;
+}
+
+// Threads per NN node group, qt targets per thread: enough to hold a chunk of
+// min(K, NN_KC<qt>) targets, and at least NT / 16 (so each group's slice of a
+// tile is at least 4 nodes).
+int nn_tpg_for(int K, int qt) {
+  const int kcm = qt * NT < 1024 ? qt * NT : 1024;
+  const int need = (std::min(K, kcm) + qt - 1) / qt;
+  int t = NT / 16;
+  while (t < need) t <<= 1;
+  return t;
+}
 
 // The device record of one query planned by G workgroups with L lanes per candidate.
 DevProblem make_problem(const pakr_system& sys, const pakr_scene& scene, const pakr_goal& goal,
-                        const pakr_params& prm, int G, int lanes, int rt = NT) {
+                        const pakr_params& prm, int G, int lanes, int rt = NT, int qt = 1) {
   DevProblem Q;
   std::memset(&Q, 0, sizeof Q);
   const int P = scene.npos;
@@ -307,6 +329,7 @@ DevProblem make_problem(const pakr_system& sys, const pakr_scene& scene, const p
   Q.G = G;
   Q.lanes = lanes;
   Q.cpb = rt / lanes;
+  Q.nn_tpg = nn_tpg_for(Q.K, qt);
   Q.G_roll = (prm.B + Q.cpb - 1) / Q.cpb;
   Q.max_path_edges = prm.max_path_edges > 0 ? prm.max_path_edges : DEFAULT_PATH_EDGES;
   Q.obs_floats = obs_floats_of(P, scene.n_box, scene.n_sphere);
@@ -602,7 +625,7 @@ int pakr_plan_init(const pakr_system* sys, const pakr_scene* scene, const float*
   pl->stream = static_cast<hipStream_t>(stream);
   pl->ticks_per_ms = di.ticks_per_ms;
   const int K = params->B / params->A;
-  pl->qt = qt_for(K);
+  pl->qt = qt_for(K, sys->d);
   pl->kfn = kernel_for(sys->id, pl->qt);
   const int of = obs_floats_of(scene->npos, scene->n_box, scene->n_sphere);
   const size_t obs_bytes = sizeof(float) * (size_t)std::max(of, 1);
@@ -669,7 +692,7 @@ int pakr_plan_init(const pakr_system* sys, const pakr_scene* scene, const float*
     }
     pl->own_ws = true;
   }
-  const DevProblem Q = make_problem(*sys, *scene, *goal, *params, G, lanes, pl->rt);
+  const DevProblem Q = make_problem(*sys, *scene, *goal, *params, G, lanes, pl->rt, pl->qt);
   pl->args = make_args(Q, static_cast<char*>(pl->ws), pl->L);
   e = upload_query(pl->args, pack_obstacles(*scene), x_init, G, pl->stream);
   if (e != hipSuccess) {

@@ -12,6 +12,9 @@ namespace pakr {
 
 constexpr int NT = 512;          // threads per workgroup (eight wave64s)
 constexpr int TILE = 64;         // tree nodes per NN tile (unit of ownership)
+// Targets per NN chunk: QT per thread in TPG = NT / NG threads, at most 1024.
+template <int QT>
+constexpr int NN_KC = QT * NT < 1024 ? QT * NT : 1024;
 constexpr int WAVE = 64;
 constexpr int MAX_SOLUTIONS = 1024;
 constexpr int MAX_GR = 1024;     // rollout workgroups per iteration
@@ -29,6 +32,7 @@ struct DevProblem {
   int n_box, n_sph, G, G_roll;
   int max_path_edges, obs_floats;
   int lanes, cpb;                  // lanes per candidate, candidates per rollout workgroup
+  int nn_tpg, pad_i;              // NN: threads per node group (NT / TPG groups)
   uint32_t key0, key1;
   float dt, h_speed, c0, vnorm_max;
   float goal_r, goal_r2, edge_duration, pad0;

@@ -184,10 +184,25 @@ __device__ __forceinline__ void block_exclusive_scan(const int* cnt, int* off, i
   __syncthreads();
 }
 
+// Per-call bookkeeping of workgroup 0, touched by its thread 0 only: device
+// clock marks (start, budget deadline, barrier-wait guard, first and last
+// solution), ticks per step of the iteration (0 NN scan, 1 wait at barrier A,
+// 2 parent reduction, 3 rollout, 4 wait at barrier B, 5 insertion and
+// bookkeeping) and counters.  In LDS rather than registers, which the
+// rollout needs.
+struct Books {
+  long long t0, deadline, guard, t_first, t_last, tk_mark;
+  long long tk[6];
+  unsigned long long c_exp, c_ins, c_nn;
+  int c_sol;
+};
+
 // LDS used by one query's loop; each kernel that runs plan_loop declares it.
 struct Smem {
   float* obs;                  // dynamic: obstacles (see any_obstacle_hit)
   float* tile;                 // [D][TILE] NN tile, 16-byte aligned
+  float* targets;              // [D][NN_KC<QT>] the NN chunk's targets
+  unsigned long long* keys;    // [NN_KC<QT>] their best keys over the node slices
   unsigned long long* best;    // [NT] parent keys of a rollout chunk
   int* cnt;                    // [MAX_GR] survivors per rollout chunk
   int* off;                    // [MAX_GR + 1] their exclusive prefix
@@ -196,16 +211,23 @@ struct Smem {
   unsigned long long* goal;
   int* fail;
   int* misc;                   // [2]
+  Books* books;
 };
 
 // The AO-x loop of one query, run by workgroup `b` of the `G` workgroups that
-// share the query (G = 1 when a workgroup plans a query alone).
-template <int SYS, int QT>
+// share the query (G = 1 when a workgroup plans a query alone).  QT targets
+// per thread in the NN scan; GROUPED: the scan may split tiles into node
+// slices (P.nn_tpg threads per slice), else one target per thread (QT = 1).
+template <int SYS, int QT, bool GROUPED>
 __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int G, const Smem& sm) {
+  static_assert(GROUPED || QT == 1, "an ungrouped scan holds one target per thread");
   constexpr int D = Sys<SYS>::D, M = Sys<SYS>::M, NP = Sys<SYS>::P;
   const DevProblem& P = a.P;
   float* const s_obs = sm.obs;
   float (*const s_tile)[TILE] = reinterpret_cast<float (*)[TILE]>(sm.tile);
+  float* const s_q = sm.targets;
+  unsigned long long* const s_key = sm.keys;
+  constexpr int KCM = NN_KC<QT>;
   unsigned long long* const s_best = sm.best;
   int* const s_cnt = sm.cnt;
   int* const s_off = sm.off;
@@ -239,25 +261,26 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
   long long it_done = 0, rounds_done = 0;
   int status = 0;
 
-  // workgroup-0 bookkeeping
-  long long t0 = 0, deadline = LLONG_MAX, guard = LLONG_MAX, t_first = -1, t_last = -1;
-  unsigned long long c_exp = 0, c_ins = 0, c_nn = 0;
-  // workgroup 0 accumulates device time per step of the iteration:
-  // 0 NN scan, 1 wait at barrier A, 2 parent reduction, 3 rollout,
-  // 4 wait at barrier B, 5 insertion and bookkeeping
-  long long tk[6] = {0, 0, 0, 0, 0, 0}, tk_mark = 0;
+  // workgroup-0 bookkeeping, kept by its thread 0 in LDS
+  Books& bk = *sm.books;
+  const bool keeper = b == 0 && tid == 0;
   auto mark = [&](int slot) {
-    if (b == 0 && tid == 0) {
+    if (keeper) {
       const long long now = wall_clock64();
-      tk[slot] += now - tk_mark;
-      tk_mark = now;
+      bk.tk[slot] += now - bk.tk_mark;
+      bk.tk_mark = now;
     }
   };
-  int c_sol = 0;
-  if (b == 0) {
-    t0 = wall_clock64();
-    if (a.budget_ticks > 0) deadline = t0 + a.budget_ticks;
-    guard = t0 + a.guard_ticks;
+  if (keeper) {
+    bk.t0 = wall_clock64();
+    bk.deadline = a.budget_ticks > 0 ? bk.t0 + a.budget_ticks : LLONG_MAX;
+    bk.guard = bk.t0 + a.guard_ticks;
+    bk.t_first = -1;
+    bk.t_last = -1;
+    bk.tk_mark = 0;
+    for (int i = 0; i < 6; ++i) bk.tk[i] = 0;
+    bk.c_exp = bk.c_ins = bk.c_nn = 0;
+    bk.c_sol = 0;
   }
   __syncthreads();
 
@@ -268,31 +291,64 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
                                                                  : nullptr;
     const int ntiles = (n + TILE - 1) / TILE;
     const int G_act = min(G, ntiles);
-    if (b == 0 && tid == 0) tk_mark = wall_clock64();
+    if (keeper) bk.tk_mark = wall_clock64();
 
     // ---------------- phase 1: targets + nearest neighbour -----------------
-    for (int base = 0; base < K; base += NT * QT) {
-      float q[QT][D];
-      float bd[QT];
-      int bi[QT];
+    // Targets are drawn once per chunk of kc <= TPG * QT and staged in LDS.
+    // Thread (grp, tl) holds the chunk's targets tl, tl + TPG, ... (QT of
+    // them, so every node read from LDS serves QT targets) and scans node
+    // slice grp (TILE / NG consecutive nodes) of each tile this workgroup
+    // owns; the NG groups' keys meet in LDS by atomic min.
+    const int TPG = GROUPED ? P.nn_tpg : NT, NG = NT / TPG, SL = TILE / NG;
+    int tid_nn = tid;
+    asm volatile("" : "+v"(tid_nn));  // derived per iteration, not held across the loop
+    const int grp = tid_nn / TPG, tl = tid_nn - grp * TPG;
+    // (one target per thread and one group: the target is drawn straight
+    // into registers and the key written straight out)
+    const bool direct = !GROUPED || (QT == 1 && NG == 1);
+    for (int base = 0; base < K; base += TPG * QT) {
+      const int kc = min(K - base, TPG * QT);
+      if (!direct) __syncthreads();  // the previous chunk's readers of s_q and s_key are done
+      for (int k = tid; k < kc && !direct; k += NT) {
+        float qs[D];
+        sample_state<D>(P, (uint32_t)(base + k), (uint32_t)iter, (uint32_t)round, qs);
 #pragma unroll
-      for (int qq = 0; qq < QT; ++qq) {
-        const int k = base + qq * NT + tid;
-        bd[qq] = INFINITY;
-        bi[qq] = 0;
-        if (k < K) {
-          sample_state<D>(P, (uint32_t)k, (uint32_t)iter, (uint32_t)round, q[qq]);
+        for (int c = 0; c < D; ++c) s_q[c * KCM + k] = qs[c];
+        if (trace != nullptr && b == 0) {
+          TraceView tv(trace, K, B, D, M);
+#pragma unroll
+          for (int c = 0; c < D; ++c) tv.targets[(size_t)(base + k) * D + c] = qs[c];
+        }
+        s_key[k] = ~0ull;
+      }
+      if (!direct) __syncthreads();
+      float q[QT][D];
+      if (direct) {
+        if (tid < kc) {
+          sample_state<D>(P, (uint32_t)(base + tid), (uint32_t)iter, (uint32_t)round, q[0]);
           if (trace != nullptr && b == 0) {
             TraceView tv(trace, K, B, D, M);
 #pragma unroll
-            for (int c = 0; c < D; ++c) tv.targets[(size_t)k * D + c] = q[qq][c];
+            for (int c = 0; c < D; ++c) tv.targets[(size_t)(base + tid) * D + c] = q[0][c];
           }
         } else {
 #pragma unroll
-          for (int c = 0; c < D; ++c) q[qq][c] = 0.0f;
+          for (int c = 0; c < D; ++c) q[0][c] = 0.0f;
         }
       }
       if (b < G_act) {
+        float bd[QT];
+        int bi[QT];
+#pragma unroll
+        for (int qq = 0; qq < QT; ++qq) {
+          const int k = qq * TPG + tl;
+          if (!direct) {
+#pragma unroll
+            for (int c = 0; c < D; ++c) q[qq][c] = k < kc ? s_q[c * KCM + k] : 0.0f;
+          }
+          bd[qq] = INFINITY;
+          bi[qq] = 0;
+        }
         // software pipeline: the next owned tile is fetched into registers
         // while the current one is scanned from LDS.  Slots past the tree end
         // get a coordinate whose squared distance overflows to +inf.
@@ -309,6 +365,7 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
           }
         };
         fetch(b);
+        const int i0 = grp * SL;
         for (int t = b; t < ntiles; t += G) {
           const int node0 = t * TILE;
           __syncthreads();
@@ -320,7 +377,7 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
           __syncthreads();
           if (t + G < ntiles) fetch(t + G);
 #pragma unroll 2
-          for (int i = 0; i < TILE; i += 4) {
+          for (int i = i0; i < i0 + SL; i += 4) {
             float4 pc[D];
 #pragma unroll
             for (int c = 0; c < D; ++c) pc[c] = *reinterpret_cast<const float4*>(&s_tile[c][i]);
@@ -337,7 +394,8 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
                 s3 = fmaf(e3, e3, s3);
               }
               // only a strictly smaller distance replaces the best, and among
-              // equal ones the lowest node index wins (the sequential rule)
+              // equal ones the lowest node index wins (the sequential rule;
+              // across slices the packed key's index decides)
               const float m = fminf(fminf(s0, s1), fminf(s2, s3));
               if (m < bd[qq]) {
                 bd[qq] = m;
@@ -346,17 +404,27 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
             }
           }
         }
+        if (direct) {
+          if (tid < kc) a.partial[(size_t)b * K + base + tid] = pack_key(bd[0], (uint32_t)bi[0]);
+        } else {
 #pragma unroll
-        for (int qq = 0; qq < QT; ++qq) {
-          const int k = base + qq * NT + tid;
-          if (k < K) a.partial[(size_t)b * K + k] = pack_key(bd[qq], (uint32_t)bi[qq]);
+          for (int qq = 0; qq < QT; ++qq) {
+            const int k = qq * TPG + tl;
+            if (k < kc) {
+              const unsigned long long key = pack_key(bd[qq], (uint32_t)bi[qq]);
+              if (NG == 1) s_key[k] = key;
+              else atomicMin(&s_key[k], key);
+            }
+          }
+          __syncthreads();
+          for (int k = tid; k < kc; k += NT) a.partial[(size_t)b * K + base + k] = s_key[k];
         }
       }
     }
     mark(0);
     if (b == 0 && tid == 0) {
       const long long now = wall_clock64();
-      const int stop = now >= deadline ? 1 : (now >= guard ? 2 : 0);
+      const int stop = now >= bk.deadline ? 1 : (now >= bk.guard ? 2 : 0);
       __hip_atomic_store(&a.hdr->stop[it_done & 1], stop, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -609,9 +677,9 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
     else if (iter + 1 >= P.max_iters_per_round) end = END_ITER_CAP;
 
     if (b == 0 && tid == 0) {
-      c_exp += (unsigned long long)B;
-      c_ins += (unsigned long long)n_ins;
-      c_nn += (unsigned long long)K * (unsigned long long)n0;
+      bk.c_exp += (unsigned long long)B;
+      bk.c_ins += (unsigned long long)n_ins;
+      bk.c_nn += (unsigned long long)K * (unsigned long long)n0;
       if (trace != nullptr) {
         int* h = trace;
         h[0] = round;
@@ -626,9 +694,9 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
         h[9] = survivors;
       }
       if (goal) {
-        const long long tnow = wall_clock64() - t0;
-        if (t_first < 0) t_first = tnow;
-        t_last = tnow;
+        const long long tnow = wall_clock64() - bk.t0;
+        if (bk.t_first < 0) bk.t_first = tnow;
+        bk.t_last = tnow;
         if (n_sol < MAX_SOLUTIONS) {
           DevSolution& so = a.sols[n_sol];
           so.round = round;
@@ -640,7 +708,7 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
           so.t = tnow;
         }
         ++n_sol;
-        ++c_sol;
+        ++bk.c_sol;
         // ExtractPath: walk the parent chain, goal first
         float* ps = a.path_states;
         float* pa = a.path_actions;
@@ -697,27 +765,31 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
     h->n_solutions = n_sol;
     h->bar_gen = gen;
     h->total_iters += (unsigned long long)it_done;
-    h->expansions += c_exp;
-    h->insertions += c_ins;
-    h->nn_pairs += c_nn;
-    h->t_start = t0;
+    h->expansions += bk.c_exp;
+    h->insertions += bk.c_ins;
+    h->nn_pairs += bk.c_nn;
+    h->t_start = bk.t0;
     h->t_end = wall_clock64();
-    h->t_first = t_first;
-    h->t_last = t_last;
+    h->t_first = bk.t_first;
+    h->t_last = bk.t_last;
     h->call_iters = (int)it_done;
     h->call_rounds = (int)rounds_done;
-    h->call_solutions = c_sol;
+    h->call_solutions = bk.c_sol;
     h->status = status | (n_sol > 0 ? PAKR_S_SOLVED : 0);
-    for (int i = 0; i < 6; ++i) h->ticks[i] = tk[i];
+    for (int i = 0; i < 6; ++i) h->ticks[i] = bk.tk[i];
   }
 }
 
-__device__ __forceinline__ Smem make_smem(float* obs, float* tile, unsigned long long* best, int* cnt,
-                                          int* off, int* wave, float* val,
-                                          unsigned long long* goal, int* fail, int* misc) {
+__device__ __forceinline__ Smem make_smem(float* obs, float* tile, float* targets,
+                                          unsigned long long* keys, unsigned long long* best,
+                                          int* cnt, int* off, int* wave, float* val,
+                                          unsigned long long* goal, int* fail, int* misc,
+                                          Books* books) {
   Smem m;
   m.obs = obs;
   m.tile = tile;
+  m.targets = targets;
+  m.keys = keys;
   m.best = best;
   m.cnt = cnt;
   m.off = off;
@@ -726,6 +798,7 @@ __device__ __forceinline__ Smem make_smem(float* obs, float* tile, unsigned long
   m.goal = goal;
   m.fail = fail;
   m.misc = misc;
+  m.books = books;
   return m;
 }
 
@@ -734,6 +807,8 @@ template <int SYS, int QT>
 __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
   extern __shared__ float s_obs[];
   __shared__ __align__(16) float s_tile[Sys<SYS>::D * TILE];
+  __shared__ float s_targets[Sys<SYS>::D * NN_KC<QT>];
+  __shared__ unsigned long long s_keys[NN_KC<QT>];
   __shared__ unsigned long long s_best[NT];
   __shared__ int s_cnt[MAX_GR];
   __shared__ int s_off[MAX_GR + 1];
@@ -742,9 +817,12 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
   __shared__ unsigned long long s_goal;
   __shared__ int s_fail;
   __shared__ int s_misc[2];
-  const Smem sm = make_smem(s_obs, s_tile, s_best, s_cnt, s_off, s_wave, s_val, &s_goal, &s_fail,
-                            s_misc);
-  plan_loop<SYS, QT>(a, blockIdx.x, gridDim.x, sm);
+  __shared__ Books s_books;
+  const Smem sm = make_smem(s_obs, s_tile, s_targets, s_keys, s_best, s_cnt, s_off, s_wave, s_val,
+                            &s_goal, &s_fail, s_misc, &s_books);
+  // (above 6 state dimensions the plan keeps the plain scan: the node-slice
+  // form costs the quadrotor's rollout code more than it saves)
+  plan_loop<SYS, QT, (Sys<SYS>::D <= 6)>(a, blockIdx.x, gridDim.x, sm);
 }
 
 // Many queries in one launch: each workgroup takes the next query from a
@@ -760,6 +838,8 @@ __global__ __launch_bounds__(NT) void k_batch(const KArgs* __restrict__ qs,
                                               int* queue) {
   extern __shared__ float s_obs[];
   __shared__ __align__(16) float s_tile[PAKR_MAX_D * TILE];
+  __shared__ float s_targets[PAKR_MAX_D * NN_KC<1>];
+  __shared__ unsigned long long s_keys[NN_KC<1>];
   __shared__ unsigned long long s_best[NT];
   __shared__ int s_cnt[MAX_GR];
   __shared__ int s_off[MAX_GR + 1];
@@ -768,28 +848,29 @@ __global__ __launch_bounds__(NT) void k_batch(const KArgs* __restrict__ qs,
   __shared__ unsigned long long s_goal;
   __shared__ int s_fail;
   __shared__ int s_misc[2];
-  __shared__ int s_q;
-  const Smem sm = make_smem(s_obs, s_tile, s_best, s_cnt, s_off, s_wave, s_val, &s_goal, &s_fail,
-                            s_misc);
+  __shared__ int s_ticket;
+  __shared__ Books s_books;
+  const Smem sm = make_smem(s_obs, s_tile, s_targets, s_keys, s_best, s_cnt, s_off, s_wave, s_val,
+                            &s_goal, &s_fail, s_misc, &s_books);
   while (true) {
-    __syncthreads();  // everyone has read the previous s_q
+    __syncthreads();  // everyone has read the previous s_ticket
     if (threadIdx.x == 0) {
       const int t = atomicAdd(queue, 1);
-      s_q = t < n_tickets ? tickets[t] : -1;
+      s_ticket = t < n_tickets ? tickets[t] : -1;
     }
     __syncthreads();
-    const int ticket = __builtin_amdgcn_readfirstlane(s_q);
+    const int ticket = __builtin_amdgcn_readfirstlane(s_ticket);
     if (ticket < 0) break;
     const KArgs& a = qs[ticket >> 5];
     const int member = ticket & 31, team = a.P.G;
     switch (a.P.system) {
-      case PAKR_DI2: plan_loop<PAKR_DI2, 1>(a, member, team, sm); break;
-      case PAKR_DI3: plan_loop<PAKR_DI3, 1>(a, member, team, sm); break;
-      case PAKR_CAR: plan_loop<PAKR_CAR, 1>(a, member, team, sm); break;
-      case PAKR_DUBINS: plan_loop<PAKR_DUBINS, 1>(a, member, team, sm); break;
-      case PAKR_UNI1: plan_loop<PAKR_UNI1, 1>(a, member, team, sm); break;
-      case PAKR_UNI2: plan_loop<PAKR_UNI2, 1>(a, member, team, sm); break;
-      default: plan_loop<PAKR_QUAD, 1>(a, member, team, sm); break;
+      case PAKR_DI2: plan_loop<PAKR_DI2, 1, true>(a, member, team, sm); break;
+      case PAKR_DI3: plan_loop<PAKR_DI3, 1, true>(a, member, team, sm); break;
+      case PAKR_CAR: plan_loop<PAKR_CAR, 1, true>(a, member, team, sm); break;
+      case PAKR_DUBINS: plan_loop<PAKR_DUBINS, 1, true>(a, member, team, sm); break;
+      case PAKR_UNI1: plan_loop<PAKR_UNI1, 1, true>(a, member, team, sm); break;
+      case PAKR_UNI2: plan_loop<PAKR_UNI2, 1, true>(a, member, team, sm); break;
+      default: plan_loop<PAKR_QUAD, 1, true>(a, member, team, sm); break;
     }
   }
 }
