@@ -58,7 +58,7 @@ enum pakr_system_id {
   PAKR_CAR = 2,  /* car: x=(px,py,theta,v,phi), u=(accel, steering rate)     */
   PAKR_QUAD = 3, /* quadrotor: x=(p, roll,pitch,yaw, body vel, body rates),
                     u=(thrust, tau_x, tau_y, tau_z)                          */
-  PAKR_DUBINS = 4, /* Dubins airplane (Sec. V-B): x=(p in R^3, yaw, pitch,
+  PAKR_DUBINS = 4, /* Dubins airplane (Sec. V-A): x=(p in R^3, yaw, pitch,
                       speed), u=(yaw rate, pitch rate, acceleration)         */
   PAKR_UNI1 = 5, /* unicycle 1 (Sec. V-C): x=(px,py,heading),
                     u=(speed, turn rate)                                     */

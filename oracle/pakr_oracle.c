@@ -167,7 +167,7 @@ static void f_quad(const orc_problem* p, const double* x, const double* u, doubl
   xd[11] = (u[3] - wxIw[2]) / Iz;
 }
 
-/* Dubins airplane (Sec. V-B): state (x, y, z, yaw, pitch, speed), controls
+/* Dubins airplane (Sec. V-A): state (x, y, z, yaw, pitch, speed), controls
  * (yaw rate, pitch rate, acceleration); the speed acts along the heading
  * given by yaw and pitch. */
 static void f_dubins(const double* x, const double* u, double* xd) {
@@ -197,6 +197,52 @@ static void f_uni2(const double* x, const double* u, double* xd) {
   xd[4] = u[1];
 }
 
+/* Acrobot (Sec. V-C): two links hanging from a fixed pivot, angles measured
+ * from the downward vertical, the second relative to the first; torque at the
+ * elbow only.  The paper names states and control only; these are the
+ * Euler-Lagrange equations of two rigid links: M(q) q'' + c(q, q') + g(q) =
+ * (0, tau), dyn = (m1, m2, l1, lc1, lc2, I1, I2, gravity), I about each centre
+ * of mass. */
+static void acrobot_terms(const orc_problem* p, const double* x, double M[2][2], double r[2],
+                          double tau) {
+  const double m1 = p->dyn[0], m2 = p->dyn[1], l1 = p->dyn[2], lc1 = p->dyn[3];
+  const double lc2 = p->dyn[4], I1 = p->dyn[5], I2 = p->dyn[6], g = p->dyn[7];
+  const double q1 = x[0], q2 = x[1], w1 = x[2], w2 = x[3];
+  const double k = m2 * l1 * lc2;
+  M[0][0] = m1 * lc1 * lc1 + m2 * (l1 * l1 + lc2 * lc2) + I1 + I2 + 2.0 * k * cos(q2);
+  M[0][1] = M[1][0] = m2 * lc2 * lc2 + I2 + k * cos(q2);
+  M[1][1] = m2 * lc2 * lc2 + I2;
+  const double c1 = -k * sin(q2) * (w2 * w2 + 2.0 * w1 * w2);
+  const double c2 = k * sin(q2) * w1 * w1;
+  const double g2 = m2 * lc2 * g * sin(q1 + q2);
+  const double g1 = (m1 * lc1 + m2 * l1) * g * sin(q1) + g2;
+  r[0] = -c1 - g1;
+  r[1] = tau - c2 - g2;
+}
+
+static void f_acrobot(const orc_problem* p, const double* x, const double* u, double* xd) {
+  double M[2][2], r[2];
+  acrobot_terms(p, x, M, r, u[0]);
+  const double det = M[0][0] * M[1][1] - M[0][1] * M[1][0];
+  xd[0] = x[2];
+  xd[1] = x[3];
+  xd[2] = (M[1][1] * r[0] - M[0][1] * r[1]) / det;
+  xd[3] = (M[0][0] * r[1] - M[1][0] * r[0]) / det;
+}
+
+/* Cart-pole (Sec. V-E lists it with an acceleration control): state (cart
+ * position, pole angle from the upward vertical, cart speed, pole rate),
+ * control the cart's acceleration; the pole is a point mass at distance
+ * dyn[0] from the pivot, dyn[1] gravity.  With the cart's acceleration
+ * prescribed the pole obeys l theta'' = g sin(theta) - a cos(theta). */
+static void f_cartpole(const orc_problem* p, const double* x, const double* u, double* xd) {
+  const double l = p->dyn[0], g = p->dyn[1];
+  xd[0] = x[2];
+  xd[1] = x[3];
+  xd[2] = u[0];
+  xd[3] = (g * sin(x[1]) - u[0] * cos(x[1])) / l;
+}
+
 void orc_dynamics(const orc_problem* p, const double* x, const double* u, double* xd) {
   switch (p->system) {
     case ORC_DI2: f_double_integrator(2, x, u, xd); break;
@@ -206,6 +252,8 @@ void orc_dynamics(const orc_problem* p, const double* x, const double* u, double
     case ORC_DUBINS: f_dubins(x, u, xd); break;
     case ORC_UNI1: f_uni1(x, u, xd); break;
     case ORC_UNI2: f_uni2(x, u, xd); break;
+    case ORC_ACROBOT: f_acrobot(p, x, u, xd); break;
+    case ORC_CARTPOLE: f_cartpole(p, x, u, xd); break;
     default: for (int i = 0; i < p->d; ++i) xd[i] = NAN;
   }
 }
@@ -868,6 +916,30 @@ static void c_dynamics(const orc_problem* p, const cplx* x, const cplx* u, cplx*
     xd[2] = x[4];
     xd[3] = u[0];
     xd[4] = u[1];
+  } else if (p->system == ORC_ACROBOT) {
+    const double m1 = p->dyn[0], m2 = p->dyn[1], l1 = p->dyn[2], lc1 = p->dyn[3];
+    const double lc2 = p->dyn[4], I1 = p->dyn[5], I2 = p->dyn[6], g = p->dyn[7];
+    const double k = m2 * l1 * lc2;
+    const cplx q1 = x[0], q2 = x[1], w1 = x[2], w2 = x[3];
+    const cplx M00 = m1 * lc1 * lc1 + m2 * (l1 * l1 + lc2 * lc2) + I1 + I2 + 2.0 * k * ccos(q2);
+    const cplx M01 = m2 * lc2 * lc2 + I2 + k * ccos(q2);
+    const cplx M11 = m2 * lc2 * lc2 + I2;
+    const cplx c1 = -k * csin(q2) * (w2 * w2 + 2.0 * w1 * w2);
+    const cplx c2 = k * csin(q2) * w1 * w1;
+    const cplx g2 = m2 * lc2 * g * csin(q1 + q2);
+    const cplx g1 = (m1 * lc1 + m2 * l1) * g * csin(q1) + g2;
+    const cplx r0 = -c1 - g1, r1 = u[0] - c2 - g2;
+    const cplx det = M00 * M11 - M01 * M01;
+    xd[0] = w1;
+    xd[1] = w2;
+    xd[2] = (M11 * r0 - M01 * r1) / det;
+    xd[3] = (M00 * r1 - M01 * r0) / det;
+  } else if (p->system == ORC_CARTPOLE) {
+    const double l = p->dyn[0], g = p->dyn[1];
+    xd[0] = x[2];
+    xd[1] = x[3];
+    xd[2] = u[0];
+    xd[3] = (g * csin(x[1]) - u[0] * ccos(x[1])) / l;
   } else {
     double mass = p->dyn[0], g = p->dyn[1], Ix = p->dyn[2], Iy = p->dyn[3], Iz = p->dyn[4];
     cplx cph = ccos(x[3]), sph = csin(x[3]), cth = ccos(x[4]), sth = csin(x[4]);

@@ -28,7 +28,7 @@ extern "C" {
 #endif
 
 enum { ORC_DI2 = 0, ORC_DI3 = 1, ORC_CAR = 2, ORC_QUAD = 3, ORC_DUBINS = 4, ORC_UNI1 = 5,
-       ORC_UNI2 = 6 };
+       ORC_UNI2 = 6, ORC_ACROBOT = 7, ORC_CARTPOLE = 8 };
 enum { ORC_COST_DURATION = 0, ORC_COST_PATH_LENGTH = 1 };
 enum { ORC_H_ADMISSIBLE = 0, ORC_H_PAPER_LITERAL = 1, ORC_H_NONE = 2 };
 

@@ -22,9 +22,9 @@ from typing import List, Optional
 import numpy as np
 
 # System identifiers shared by the C ABI (include/pakr.h) and the reference.
-DI2, DI3, CAR, QUAD, DUBINS, UNI1, UNI2 = 0, 1, 2, 3, 4, 5, 6
+DI2, DI3, CAR, QUAD, DUBINS, UNI1, UNI2, ACROBOT, CARTPOLE = 0, 1, 2, 3, 4, 5, 6, 7, 8
 SYSTEM_NAMES = {DI2: "di2", DI3: "di3", CAR: "car", QUAD: "quad", DUBINS: "dubins",
-                UNI1: "uni1", UNI2: "uni2"}
+                UNI1: "uni1", UNI2: "uni2", ACROBOT: "acrobot", CARTPOLE: "cartpole"}
 
 # Cost kinds (problem statement, Sec. III: path length or time optimality).
 COST_DURATION, COST_PATH_LENGTH = 0, 1
@@ -160,6 +160,32 @@ def system_table(system: int, ws_lo, ws_hi) -> dict:
                     u_lo=[-0.25, -0.25], u_hi=[0.25, 0.25],
                     lim_lo=[-inf, -inf, -inf, -0.5, -0.5], lim_hi=[inf, inf, inf, 0.5, 0.5],
                     vnorm_max=0.0, h_speed=0.5)
+    if system == ACROBOT:
+        # acrobot: configuration (shoulder angle from hanging, elbow angle);
+        # uniform links m 1, length 1, centre of mass at 0.5, I = 1/12 about
+        # it; |joint rates| <= 8, |elbow torque| <= 10
+        rate = 8.0
+        s_lo = [ws_lo[0], ws_lo[1], -rate, -rate]
+        s_hi = [ws_hi[0], ws_hi[1], rate, rate]
+        dyn = np.zeros(8)
+        dyn[:8] = [1.0, 1.0, 1.0, 0.5, 0.5, 1.0 / 12.0, 1.0 / 12.0, 9.81]
+        return dict(d=4, m=1, npos=2, dyn=dyn, sample_lo=s_lo, sample_hi=s_hi,
+                    u_lo=[-10.0], u_hi=[10.0], lim_lo=[-inf, -inf, -rate, -rate],
+                    lim_hi=[inf, inf, rate, rate], vnorm_max=0.0,
+                    h_speed=float(np.float32(math.sqrt(2.0) * rate)))
+    if system == CARTPOLE:
+        # cart-pole: configuration (cart position, pole angle from upright);
+        # pole length 1, g 9.81; |cart speed| <= 4, |pole rate| <= 10, cart
+        # acceleration in [-10, 10]
+        vmax, wmax = 4.0, 10.0
+        s_lo = [ws_lo[0], ws_lo[1], -vmax, -wmax]
+        s_hi = [ws_hi[0], ws_hi[1], vmax, wmax]
+        dyn = np.zeros(8)
+        dyn[:2] = [1.0, 9.81]
+        return dict(d=4, m=1, npos=2, dyn=dyn, sample_lo=s_lo, sample_hi=s_hi,
+                    u_lo=[-10.0], u_hi=[10.0], lim_lo=[-inf, -inf, -vmax, -wmax],
+                    lim_hi=[inf, inf, vmax, wmax], vnorm_max=0.0,
+                    h_speed=float(np.float32(math.hypot(vmax, wmax))))
     raise ValueError(f"unknown system {system}")
 
 
@@ -287,7 +313,7 @@ CONFIGS = {"c1": config_c1, "c2": config_c2, "c3": config_c3, "c4": config_c4}
 
 
 # ----------------------------------------------------------------------------
-# The paper's other analytic systems (Sec. V-B, V-C) on scenes of the same kind.
+# The paper's other analytic systems (Sec. V-A, V-C, V-E) on scenes of the same kind.
 # ----------------------------------------------------------------------------
 
 def config_dubins(seed: int = 0, **over) -> Problem:
@@ -329,7 +355,36 @@ def config_uni2(seed: int = 0, **over) -> Problem:
     return build_problem(UNI2, [0, 0], [10, 10], *scene, start, goal_c, goal_r, **kw)
 
 
-MORE_CONFIGS = {"dubins": config_dubins, "uni1": config_uni1, "uni2": config_uni2}
+def _no_obstacles(npos: int):
+    return (np.zeros((0, npos)), np.zeros((0, npos)), np.zeros((0, npos)), np.zeros(0))
+
+
+def config_acrobot(seed: int = 0, **over) -> Problem:
+    """Acrobot swing-up: from hanging at rest to the upright configuration
+    (shoulder pi, elbow 0) within 0.3 rad; configuration box [-2 pi, 2 pi]^2, no
+    obstacles; B 1024, A 8, T 10, dt .02."""
+    lo, hi = [-2 * math.pi, -2 * math.pi], [2 * math.pi, 2 * math.pi]
+    kw = dict(B=1024, A=8, T=10, dt=np.float32(0.02), n_cap=131072, cost_kind=COST_DURATION,
+              seed=seed, name="acrobot")
+    kw.update(over)
+    return build_problem(ACROBOT, lo, hi, *_no_obstacles(2), [0.0, 0.0, 0.0, 0.0],
+                         [math.pi, 0.0], 0.3, **kw)
+
+
+def config_cartpole(seed: int = 0, **over) -> Problem:
+    """Cart-pole swing-up: from the pole hanging (angle pi) at rest to upright
+    with the cart near the centre (within 0.3 of (0, 0)); cart in [-2.5, 2.5],
+    angle in [-2 pi, 2 pi], no obstacles; B 1024, A 8, T 10, dt .02."""
+    lo, hi = [-2.5, -2 * math.pi], [2.5, 2 * math.pi]
+    kw = dict(B=1024, A=8, T=10, dt=np.float32(0.02), n_cap=131072, cost_kind=COST_DURATION,
+              seed=seed, name="cartpole")
+    kw.update(over)
+    return build_problem(CARTPOLE, lo, hi, *_no_obstacles(2), [0.0, math.pi, 0.0, 0.0],
+                         [0.0, 0.0], 0.3, **kw)
+
+
+MORE_CONFIGS = {"dubins": config_dubins, "uni1": config_uni1, "uni2": config_uni2,
+                "acrobot": config_acrobot, "cartpole": config_cartpole}
 
 # Per-system planner settings used for the mixed batch.
 _BATCH_SETTINGS = {

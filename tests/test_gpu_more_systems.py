@@ -1,4 +1,4 @@
-"""The Dubins airplane and the two unicycles (Sec. V-B, V-C) on the GPU.
+"""The Dubins airplane and the two unicycles (Sec. V-A, V-C) on the GPU.
 
 The same bars as the four main systems: step parity of the planner against the
 FP64 reference (several NN tiles and rollout workgroups, a ragged batch), the

@@ -1,16 +1,22 @@
-"""Pins for the oracle's Dubins airplane and unicycle dynamics (Sec. V-B, V-C).
+"""Pins for the oracle's Dubins airplane, unicycle, acrobot and cart-pole
+dynamics (Sec. V-A, V-C, V-E).
 
 The paper names the states and controls only; the models are the usual
-kinematic ones.  They are pinned by their exact solutions: straight lines
-(polynomial in time, where RK4 is exact), constant-rate turns (circles and
-helices, approached with observed order 4), and scipy's DOP853 as an
-independent integrator under arbitrary held controls.
+kinematic ones for the airplane and the unicycles and the rigid-body ones for
+the acrobot and the cart-pole.  They are pinned by exact solutions: straight
+lines (polynomial in time, where RK4 is exact), constant-rate turns (circles
+and helices, approached with observed order 4), a pole leaning at the angle of
+the effective gravity, the nonlinear pendulum's Jacobi-elliptic solution; by
+the acrobot's Euler-Lagrange equations taken numerically from its kinematics
+and energy (no closed form retyped); by energy conservation; and by scipy's
+DOP853 as an independent integrator under arbitrary held controls.
 """
 import math
 
 import numpy as np
 import pytest
 from scipy.integrate import solve_ivp
+from scipy.special import ellipj, ellipk
 
 import oracle
 from paper_2607_03987_amd import workloads as W
@@ -96,16 +102,111 @@ def test_dubins_helix_fourth_order():
     assert 12.0 < e1 / e2 < 20.0
 
 
+def _acrobot_energy(dyn, x):
+    """Kinetic plus potential energy from the link kinematics (height up)."""
+    m1, m2, l1, lc1, lc2, I1, I2, g = dyn
+    q1, q2, w1, w2 = x
+    # centres of mass; angles from the downward vertical, the second relative
+    p1 = np.array([lc1 * math.sin(q1), -lc1 * math.cos(q1)])
+    v1 = np.array([lc1 * math.cos(q1), lc1 * math.sin(q1)]) * w1
+    p2 = np.array([l1 * math.sin(q1) + lc2 * math.sin(q1 + q2),
+                   -l1 * math.cos(q1) - lc2 * math.cos(q1 + q2)])
+    v2 = (np.array([l1 * math.cos(q1), l1 * math.sin(q1)]) * w1
+          + np.array([lc2 * math.cos(q1 + q2), lc2 * math.sin(q1 + q2)]) * (w1 + w2))
+    T = 0.5 * m1 * v1 @ v1 + 0.5 * I1 * w1 ** 2 + 0.5 * m2 * v2 @ v2 + 0.5 * I2 * (w1 + w2) ** 2
+    return T, m1 * g * p1[1] + m2 * g * p2[1]
+
+
+def _acrobot_euler_lagrange(dyn, x, tau):
+    """q'' from d/dt dL/dq' - dL/dq = (0, tau), with every derivative of
+    L = T - V taken by central differences of the energy function."""
+    def L(q, w):
+        T, V = _acrobot_energy(dyn, np.concatenate([q, w]))
+        return T - V
+    q, w = np.asarray(x[:2], float), np.asarray(x[2:], float)
+    # steps: L is quadratic in q', so differences in q' are exact for any step
+    # (a large one keeps rounding small); differences in q are O(hq^2)
+    hw, hq = 0.1, 1e-4
+    E = np.eye(2)
+    M = np.array([[(L(q, w + hw * (E[i] + E[j])) - L(q, w + hw * (E[i] - E[j]))
+                    - L(q, w - hw * (E[i] - E[j])) + L(q, w - hw * (E[i] + E[j]))) / (4 * hw * hw)
+                   for j in range(2)] for i in range(2)])
+    dLdq = np.array([(L(q + hq * E[i], w) - L(q - hq * E[i], w)) / (2 * hq) for i in range(2)])
+    # d/dt dL/dq' = M q'' + (d2L/dq' dq) q'
+    C = np.array([[(L(q + hq * E[j], w + hw * E[i]) - L(q + hq * E[j], w - hw * E[i])
+                    - L(q - hq * E[j], w + hw * E[i]) + L(q - hq * E[j], w - hw * E[i]))
+                   / (4 * hq * hw) for j in range(2)] for i in range(2)])
+    return np.linalg.solve(M, np.array([0.0, tau]) + dLdq - C @ w)
+
+
+@pytest.mark.parametrize("x,tau", [([0.3, -0.7, 1.1, -2.0], 0.0), ([2.5, 1.2, -3.0, 0.4], 4.0),
+                                   ([-1.0, 2.9, 0.0, 5.5], -7.5), ([0.0, 0.0, 0.0, 0.0], 10.0)])
+def test_acrobot_matches_euler_lagrange_of_its_kinematics(x, tau):
+    cp = cp_of("acrobot")
+    dyn = np.asarray(cp.prob.dyn, np.float64)
+    got = oracle.dynamics(cp, np.array(x), np.array([tau]))
+    np.testing.assert_allclose(got[:2], x[2:], rtol=0, atol=0)
+    np.testing.assert_allclose(got[2:], _acrobot_euler_lagrange(dyn, x, tau), rtol=1e-7, atol=1e-7)
+
+
+def test_acrobot_conserves_energy_without_torque():
+    cp = cp_of("acrobot")
+    dyn = np.asarray(cp.prob.dyn, np.float64)
+    x0 = np.array([2.0, -1.0, 0.5, 1.5])
+    traj = oracle.rollout(cp, x0, np.zeros(1), 2000, 1e-3)
+    E = [sum(_acrobot_energy(dyn, x)) for x in traj[::100]]
+    assert np.ptp(E) < 1e-8 * max(1.0, abs(E[0]))
+    assert np.abs(traj[-1] - x0).max() > 0.5  # it did move
+
+
+def test_cartpole_leans_at_the_effective_gravity_angle():
+    """Constant acceleration a: the pole at atan(a/g) from upright, at rest,
+    stays there while the cart moves as x0 + v0 t + a t^2 / 2 (exact for RK4)."""
+    cp = cp_of("cartpole")
+    a, g = 3.0, float(cp.prob.dyn[1])
+    th = math.atan2(a, g)
+    x0 = np.array([0.5, th, -0.2, 0.0])
+    traj = oracle.rollout(cp, x0, np.array([a]), 50, 0.02)
+    for t in range(51):
+        tt = 0.02 * t
+        np.testing.assert_allclose(traj[t], [0.5 - 0.2 * tt + 0.5 * a * tt * tt, th, -0.2 + a * tt, 0.0],
+                                   rtol=1e-12, atol=1e-12)
+
+
+def test_cartpole_hanging_pole_is_the_nonlinear_pendulum():
+    """a = 0, released at rest phi0 from hanging: phi(t) = 2 asin(k sn(K - w t, k^2)),
+    k = sin(phi0 / 2), w = sqrt(g / l) (Jacobi elliptic solution)."""
+    cp = cp_of("cartpole")
+    l, g = float(cp.prob.dyn[0]), float(cp.prob.dyn[1])
+    phi0 = 1.2
+    x0 = np.array([0.0, math.pi + phi0, 0.0, 0.0])
+    h, n = 1e-3, 3000
+    traj = oracle.rollout(cp, x0, np.zeros(1), n, h)
+    k = math.sin(phi0 / 2)
+    K = ellipk(k * k)
+    w = math.sqrt(g / l)
+    for t in range(0, n + 1, 250):
+        sn = ellipj(K - w * h * t, k * k)[0]
+        assert traj[t, 1] - math.pi == pytest.approx(2 * math.asin(k * sn), abs=1e-9)
+    E = 0.5 * l * l * traj[:, 3] ** 2 + g * l * np.cos(traj[:, 1])
+    assert np.ptp(E) < 1e-9
+
+
 @pytest.mark.parametrize("name,u", [("uni1", [0.45, -0.35]), ("uni2", [0.2, -0.15]),
-                                    ("dubins", [0.8, -0.3, 0.4])])
+                                    ("dubins", [0.8, -0.3, 0.4]), ("acrobot", [3.0]),
+                                    ("cartpole", [-4.0])])
 def test_matches_dop853(name, u):
     cp = cp_of(name)
     prob = cp.prob
     x0 = np.asarray(prob.x_init, np.float64).copy()
     if name == "uni2":
         x0[3:] = [0.3, 0.1]
+    if name in ("acrobot", "cartpole"):
+        x0[2:] = [0.7, -1.3]
     u = np.asarray(u, np.float64)
-    h, n = 0.01, 200
+    # the pendulum systems accelerate faster: a smaller step keeps RK4's error
+    # below the tolerance over the same 2 s
+    h, n = (0.001, 2000) if name in ("acrobot", "cartpole") else (0.01, 200)
 
     def rhs(_, x):
         return oracle.dynamics(cp, x, u)
@@ -116,7 +217,8 @@ def test_matches_dop853(name, u):
 
 
 ALL = [("c1", W.CONFIGS), ("c2", W.CONFIGS), ("c3", W.CONFIGS), ("c4", W.CONFIGS),
-       ("dubins", W.MORE_CONFIGS), ("uni1", W.MORE_CONFIGS), ("uni2", W.MORE_CONFIGS)]
+       ("dubins", W.MORE_CONFIGS), ("uni1", W.MORE_CONFIGS), ("uni2", W.MORE_CONFIGS),
+       ("acrobot", W.MORE_CONFIGS), ("cartpole", W.MORE_CONFIGS)]
 
 
 def _controls(prob, M, rng, spread):
@@ -143,7 +245,7 @@ def test_refinement_dynamics_equal_the_rollout(name, table):
     assert oracle.traj_cost(cp, rp, x, U) == pytest.approx(want, rel=1e-12)
 
 
-@pytest.mark.parametrize("name", ["dubins", "uni1", "uni2"])
+@pytest.mark.parametrize("name", ["dubins", "uni1", "uni2", "acrobot", "cartpole"])
 def test_refinement_gradient_matches_finite_differences(name):
     prob = W.MORE_CONFIGS[name]().replace(T=5)
     cp = oracle.CProblem(prob)
