@@ -62,8 +62,12 @@ enum pakr_system_id {
                       speed), u=(yaw rate, pitch rate, acceleration)         */
   PAKR_UNI1 = 5, /* unicycle 1 (Sec. V-C): x=(px,py,heading),
                     u=(speed, turn rate)                                     */
-  PAKR_UNI2 = 6  /* unicycle 2 (Sec. V-C): x=(px,py,heading,speed,turn rate),
+  PAKR_UNI2 = 6, /* unicycle 2 (Sec. V-C): x=(px,py,heading,speed,turn rate),
                     u=(acceleration, angular acceleration)                   */
+  PAKR_ACROBOT = 7, /* acrobot (Sec. V-C): x=(shoulder angle from hanging,
+                       elbow angle, their rates), u=(elbow torque)           */
+  PAKR_CARTPOLE = 8 /* cart-pole (Sec. V-E): x=(cart position, pole angle from
+                       upright, cart speed, pole rate), u=(cart acceleration) */
 };
 
 /* Cost J (Sec. III): trajectory duration or path length of the positions. */
@@ -103,7 +107,10 @@ enum pakr_status_bits {
 typedef struct pakr_system {
   int id;                          /* pakr_system_id                                  */
   int d, m;                        /* state / control dimension, must match id        */
-  float dyn[8];                    /* CAR: [0]=wheelbase; QUAD: mass, g, Ixx, Iyy, Izz */
+  float dyn[8];                    /* CAR: [0]=wheelbase; QUAD: mass, g, Ixx, Iyy, Izz;
+                                      ACROBOT: m1, m2, l1, lc1, lc2, I1, I2, g (lc: pivot
+                                      to centre of mass, I about it); CARTPOLE: pole
+                                      length, g                                       */
   float sample_lo[PAKR_MAX_D];     /* SampleStates box per state dimension            */
   float sample_hi[PAKR_MAX_D];
   float u_lo[PAKR_MAX_M];          /* control box U                                   */

@@ -29,7 +29,7 @@ struct Layout {
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 int sys_npos(int id) {
-  return (id == PAKR_DI2 || id == PAKR_CAR || id == PAKR_UNI1 || id == PAKR_UNI2) ? 2 : 3;
+  return (id == PAKR_DI3 || id == PAKR_QUAD || id == PAKR_DUBINS) ? 3 : 2;
 }
 int sys_d(int id) {
   switch (id) {
@@ -40,6 +40,8 @@ int sys_d(int id) {
     case PAKR_DUBINS: return 6;
     case PAKR_UNI1: return 3;
     case PAKR_UNI2: return 5;
+    case PAKR_ACROBOT: return 4;
+    case PAKR_CARTPOLE: return 4;
   }
   return -1;
 }
@@ -52,21 +54,25 @@ int sys_m(int id) {
     case PAKR_DUBINS: return 3;
     case PAKR_UNI1: return 2;
     case PAKR_UNI2: return 2;
+    case PAKR_ACROBOT: return 1;
+    case PAKR_CARTPOLE: return 1;
   }
   return -1;
 }
 
 // Estimated instructions of one evaluation of f beyond its linear part: the
 // transcendental functions dominate (three sincos and a reciprocal for the
-// quadrotor, a sincos and a tangent for the car, one or two sincos for the
-// Dubins airplane and the unicycles).
+// quadrotor, a sincos and a tangent for the car, two sincos and a division
+// for the acrobot, one or two sincos for the others).
 double f_eval_of(int id) {
   switch (id) {
     case PAKR_QUAD: return 204.0;
     case PAKR_CAR: return 128.0;
     case PAKR_DUBINS: return 120.0;
+    case PAKR_ACROBOT: return 140.0;
     case PAKR_UNI1:
-    case PAKR_UNI2: return 64.0;
+    case PAKR_UNI2:
+    case PAKR_CARTPOLE: return 64.0;
   }
   return 0.0;
 }
@@ -170,7 +176,7 @@ bool host_state_ok(const pakr_system& s, const pakr_scene& sc, const float* x) {
 
 // System record checks (and the scene's position dimension).
 std::string validate_system(const pakr_system* s, const pakr_scene* sc) {
-  if (s->id < PAKR_DI2 || s->id > PAKR_UNI2) return "unknown system id";
+  if (s->id < PAKR_DI2 || s->id > PAKR_CARTPOLE) return "unknown system id";
   if (s->d != sys_d(s->id) || s->m != sys_m(s->id)) return "d/m do not match the system";
   if (sc->npos != sys_npos(s->id)) return "scene npos does not match the system";
   for (int i = 0; i < s->d; ++i) {
@@ -192,6 +198,15 @@ std::string validate_system(const pakr_system* s, const pakr_scene* sc) {
   if (s->id == PAKR_QUAD && !(s->dyn[0] > 0.0f && s->dyn[2] > 0.0f && s->dyn[3] > 0.0f &&
                              s->dyn[4] > 0.0f && std::isfinite(s->dyn[1])))
     return "quadrotor mass and inertia must be > 0";
+  if (s->id == PAKR_ACROBOT) {
+    for (int i = 0; i < 7; ++i)
+      if (!(s->dyn[i] > 0.0f) || !std::isfinite(s->dyn[i]))
+        return "acrobot masses, lengths and inertias must be > 0";
+    if (!std::isfinite(s->dyn[7])) return "acrobot gravity must be finite";
+  }
+  if (s->id == PAKR_CARTPOLE && !(s->dyn[0] > 0.0f && std::isfinite(s->dyn[0]) &&
+                                 std::isfinite(s->dyn[1])))
+    return "cart-pole pole length must be > 0";
   return std::string();
 }
 
@@ -282,6 +297,8 @@ const void* kernel_for(int sys, int qt) {
     case PAKR_DUBINS: return pick_kernel<PAKR_DUBINS>(qt);
     case PAKR_UNI1: return pick_kernel<PAKR_UNI1>(qt);
     case PAKR_UNI2: return pick_kernel<PAKR_UNI2>(qt);
+    case PAKR_ACROBOT: return pick_kernel<PAKR_ACROBOT>(qt);
+    case PAKR_CARTPOLE: return pick_kernel<PAKR_CARTPOLE>(qt);
     default: return pick_kernel<PAKR_QUAD>(qt);
   }
 }
@@ -1256,6 +1273,8 @@ const void* traj_kernel_for(int sys, int which) {
     case PAKR_DUBINS: return traj_kernel<PAKR_DUBINS>(which);
     case PAKR_UNI1: return traj_kernel<PAKR_UNI1>(which);
     case PAKR_UNI2: return traj_kernel<PAKR_UNI2>(which);
+    case PAKR_ACROBOT: return traj_kernel<PAKR_ACROBOT>(which);
+    case PAKR_CARTPOLE: return traj_kernel<PAKR_CARTPOLE>(which);
     default: return traj_kernel<PAKR_QUAD>(which);
   }
 }

@@ -237,6 +237,33 @@ __device__ __forceinline__ void dynamics_vjp(const DevProblem& P, const float* x
     gx[4] += w[2];
     gu[0] += w[3];
     gu[1] += w[4];
+  } else if constexpr (SYS == PAKR_CARTPOLE) {
+    const float l = P.dyn[0], g = P.dyn[1];
+    const float s = tg.s[0], c = tg.c[0];
+    gx[1] += w[3] * (g * c + u[0] * s) / l;
+    gx[2] += w[0];
+    gx[3] += w[1];
+    gu[0] += w[2] - w[3] * c / l;
+  } else if constexpr (SYS == PAKR_ACROBOT) {
+    // q'' = M^-1 r: with lambda = M^-1 (w2, w3) (M symmetric), the weights
+    // reach r as lambda and M as -lambda q''^T; M depends on the elbow angle
+    // only, r on both angles, both rates and the torque
+    const float m1 = P.dyn[0], m2 = P.dyn[1], l1 = P.dyn[2], lc1 = P.dyn[3];
+    const float lc2 = P.dyn[4], g = P.dyn[7];
+    const float k = m2 * l1 * lc2, gm2 = m2 * lc2 * g, gm1 = (m1 * lc1 + m2 * l1) * g;
+    const AcrobotTerms t = acrobot_terms(P, x, u[0], tg);
+    const float v1 = x[2], v2 = x[3];
+    const float s2 = tg.s[1], c2 = tg.c[1];
+    const float l0 = (t.m11 * w[2] - t.m01 * w[3]) * t.inv_det;
+    const float lm = (t.m00 * w[3] - t.m01 * w[2]) * t.inv_det;
+    // dM/d(elbow) = -k s2 [[2, 1], [1, 0]]
+    const float dM = l0 * (2.0f * t.a1 + t.a2) + lm * t.a1;
+    gx[0] += -l0 * (gm1 * tg.c[0] + gm2 * tg.c[2]) - lm * gm2 * tg.c[2];
+    gx[1] += l0 * (k * c2 * (v2 * v2 + 2.0f * v1 * v2) - gm2 * tg.c[2]) -
+             lm * (k * c2 * v1 * v1 + gm2 * tg.c[2]) + k * s2 * dM;
+    gx[2] += w[0] + 2.0f * k * s2 * (l0 * v2 - lm * v1);
+    gx[3] += w[1] + 2.0f * k * s2 * l0 * (v2 + v1);
+    gu[0] += lm;
   } else {
     static_assert(SYS == PAKR_QUAD, "unknown system");
     const float inv_m = 1.0f / P.dyn[0], g = P.dyn[1];
@@ -302,9 +329,10 @@ __device__ __forceinline__ float lane_value(float v, int l) {
 
 template <int SYS>
 __device__ __forceinline__ Trig wave_trig(const float* x, int lane) {
-  if constexpr (SYS == PAKR_DUBINS) {
-    // yaw on lane 0, pitch on lane 1
-    const float ang = lane == 0 ? x[3] : x[4];
+  if constexpr (SYS == PAKR_DUBINS || SYS == PAKR_ACROBOT) {
+    // two angles: lane 0 and lane 1 (Dubins yaw and pitch, acrobot joints)
+    constexpr int A0 = SYS == PAKR_DUBINS ? 3 : 0;
+    const float ang = lane == 0 ? x[A0] : x[A0 + 1];
     float sv, cv;
     sincosf(ang, &sv, &cv);
     Trig g;
@@ -313,7 +341,13 @@ __device__ __forceinline__ Trig wave_trig(const float* x, int lane) {
       g.s[k] = lane_value(sv, k);
       g.c[k] = lane_value(cv, k);
     }
-    g.s[2] = g.c[2] = g.t = 0.0f;
+    if constexpr (SYS == PAKR_ACROBOT) {  // angle sum, as trig_of takes it
+      g.s[2] = g.s[0] * g.c[1] + g.c[0] * g.s[1];
+      g.c[2] = g.c[0] * g.c[1] - g.s[0] * g.s[1];
+    } else {
+      g.s[2] = g.c[2] = 0.0f;
+    }
+    g.t = 0.0f;
     return g;
   } else if constexpr (SYS == PAKR_QUAD) {
     const float ang = lane == 0 ? x[3] : (lane == 1 ? x[4] : x[5]);

@@ -144,11 +144,14 @@ template <> struct Sys<PAKR_QUAD> { static constexpr int D = 12, M = 4, P = 3, C
 template <> struct Sys<PAKR_DUBINS> { static constexpr int D = 6, M = 3, P = 3, CH = 4; };
 template <> struct Sys<PAKR_UNI1> { static constexpr int D = 3, M = 2, P = 2, CH = 8; };
 template <> struct Sys<PAKR_UNI2> { static constexpr int D = 5, M = 2, P = 2, CH = 8; };
+template <> struct Sys<PAKR_ACROBOT> { static constexpr int D = 4, M = 1, P = 2, CH = 8; };
+template <> struct Sys<PAKR_CARTPOLE> { static constexpr int D = 4, M = 1, P = 2, CH = 8; };
 
 // The trigonometric values f needs at one state: the car's heading sine and
 // cosine and steering tangent, the quadrotor's roll, pitch and yaw sines and
 // cosines, the Dubins airplane's yaw and pitch sines and cosines, the
-// unicycles' heading sine and cosine.  Computed once per evaluation (and, in the adjoint, shared between
+// unicycles' heading and the cart-pole's pole angle sine and cosine, the
+// acrobot's two joint angles and their sum.  Computed once per evaluation (and, in the adjoint, shared between
 // an RK4 stage's evaluation of f and its vector-Jacobian product).
 struct Trig {
   float s[3], c[3], t;
@@ -168,8 +171,43 @@ __device__ __forceinline__ Trig trig_of(const float* x) {
     sincosf(x[4], &g.s[1], &g.c[1]);
   } else if constexpr (SYS == PAKR_UNI1 || SYS == PAKR_UNI2) {
     sincosf(x[2], &g.s[0], &g.c[0]);
+  } else if constexpr (SYS == PAKR_CARTPOLE) {
+    sincosf(x[1], &g.s[0], &g.c[0]);
+  } else if constexpr (SYS == PAKR_ACROBOT) {
+    sincosf(x[0], &g.s[0], &g.c[0]);
+    sincosf(x[1], &g.s[1], &g.c[1]);
+    g.s[2] = g.s[0] * g.c[1] + g.c[0] * g.s[1];  // angle sum
+    g.c[2] = g.c[0] * g.c[1] - g.s[0] * g.s[1];
   }
   return g;
+}
+
+// The acrobot's mass matrix (symmetric, a function of the elbow angle), the
+// right-hand side r = (0, tau) - c - g and the joint accelerations M^-1 r;
+// dyn = (m1, m2, l1, lc1, lc2, I1, I2, gravity).
+struct AcrobotTerms {
+  float m00, m01, m11, inv_det, r0, r1, a1, a2;
+};
+
+__device__ __forceinline__ AcrobotTerms acrobot_terms(const DevProblem& P, const float* x,
+                                                      float tau, const Trig& tg) {
+  const float m1 = P.dyn[0], m2 = P.dyn[1], l1 = P.dyn[2], lc1 = P.dyn[3];
+  const float lc2 = P.dyn[4], I1 = P.dyn[5], I2 = P.dyn[6], g = P.dyn[7];
+  const float k = m2 * l1 * lc2;
+  const float b = m2 * lc2 * lc2 + I2;
+  const float v1 = x[2], v2 = x[3];
+  AcrobotTerms t;
+  t.m00 = m1 * lc1 * lc1 + m2 * l1 * l1 + b + I1 + 2.0f * k * tg.c[1];
+  t.m01 = b + k * tg.c[1];
+  t.m11 = b;
+  const float g2 = m2 * lc2 * g * tg.s[2];
+  const float g1 = (m1 * lc1 + m2 * l1) * g * tg.s[0] + g2;
+  t.r0 = k * tg.s[1] * (v2 * v2 + 2.0f * v1 * v2) - g1;
+  t.r1 = tau - k * tg.s[1] * v1 * v1 - g2;
+  t.inv_det = 1.0f / (t.m00 * t.m11 - t.m01 * t.m01);
+  t.a1 = (t.m11 * t.r0 - t.m01 * t.r1) * t.inv_det;
+  t.a2 = (t.m00 * t.r1 - t.m01 * t.r0) * t.inv_det;
+  return t;
 }
 
 // x' = f(x, u), Eq. (1), given the state's trigonometric values.
@@ -213,6 +251,20 @@ __device__ __forceinline__ void dynamics_trig(const DevProblem& P, const float* 
     xd[2] = x[4];
     xd[3] = u[0];
     xd[4] = u[1];
+  } else if constexpr (SYS == PAKR_ACROBOT) {
+    // M(q) q'' = (0, tau) - c(q, q') - g(q): two rigid links, elbow torque
+    const AcrobotTerms t = acrobot_terms(P, x, u[0], tg);
+    xd[0] = x[2];
+    xd[1] = x[3];
+    xd[2] = t.a1;
+    xd[3] = t.a2;
+  } else if constexpr (SYS == PAKR_CARTPOLE) {
+    // point-mass pole on a cart whose acceleration is the control
+    const float l = P.dyn[0], g = P.dyn[1];
+    xd[0] = x[2];
+    xd[1] = x[3];
+    xd[2] = u[0];
+    xd[3] = (g * tg.s[0] - u[0] * tg.c[0]) / l;
   } else {
     static_assert(SYS == PAKR_QUAD, "unknown system");
     // quadrotor, Z-Y-X Euler angles; body-frame velocity (ub,vb,wb), rates (p,q,r)

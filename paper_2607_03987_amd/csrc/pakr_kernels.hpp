@@ -870,6 +870,8 @@ __global__ __launch_bounds__(NT) void k_batch(const KArgs* __restrict__ qs,
       case PAKR_DUBINS: plan_loop<PAKR_DUBINS, 1, true>(a, member, team, sm); break;
       case PAKR_UNI1: plan_loop<PAKR_UNI1, 1, true>(a, member, team, sm); break;
       case PAKR_UNI2: plan_loop<PAKR_UNI2, 1, true>(a, member, team, sm); break;
+      case PAKR_ACROBOT: plan_loop<PAKR_ACROBOT, 1, true>(a, member, team, sm); break;
+      case PAKR_CARTPOLE: plan_loop<PAKR_CARTPOLE, 1, true>(a, member, team, sm); break;
       default: plan_loop<PAKR_QUAD, 1, true>(a, member, team, sm); break;
     }
   }

@@ -1,10 +1,11 @@
-"""The Dubins airplane and the two unicycles (Sec. V-A, V-C) on the GPU.
+"""The Dubins airplane, the two unicycles, the acrobot and the cart-pole
+(Sec. V-A, V-C, V-E) on the GPU.
 
 The same bars as the four main systems: step parity of the planner against the
 FP64 reference (several NN tiles and rollout workgroups, a ragged batch), the
 refinement's rollout and adjoint against the oracle's objective and
 complex-step gradient, a path the planner extracts checked edge by edge by the
-oracle, and batched planning of a mix that holds all seven systems, bit-equal
+oracle, and batched planning of a mix that holds all nine systems, bit-equal
 to planning each query alone.
 """
 import numpy as np
@@ -30,6 +31,10 @@ def _log(msg):
     ("uni1", dict(B=300, A=3, n_cap=8000, seed=2), 12),
     ("uni2", dict(B=1024, A=8, n_cap=40000), 15),
     ("uni2", dict(B=300, A=3, n_cap=8000, seed=2), 12),
+    ("acrobot", dict(B=1024, A=8, n_cap=40000), 15),
+    ("acrobot", dict(B=300, A=3, n_cap=8000, seed=2), 12),
+    ("cartpole", dict(B=1024, A=8, n_cap=40000), 15),
+    ("cartpole", dict(B=300, A=3, n_cap=8000, seed=2), 12),
 ])
 def test_step_parity(name, kw, iters):
     prob = W.MORE_CONFIGS[name](**kw)
@@ -53,7 +58,8 @@ def _controls(prob, n, M, rng, spread):
     return (mid + spread * half * rng.uniform(-1, 1, (n, M, prob.m))).astype(np.float32)
 
 
-@pytest.mark.parametrize("name,T,M", [("dubins", 20, 5), ("uni1", 10, 6), ("uni2", 10, 6)])
+@pytest.mark.parametrize("name,T,M", [("dubins", 20, 5), ("uni1", 10, 6), ("uni2", 10, 6),
+                                      ("acrobot", 10, 6), ("cartpole", 10, 6)])
 def test_forward_and_adjoint_match_oracle(name, T, M):
     prob = W.MORE_CONFIGS[name]().replace(T=T)
     print(f"case refine {name} T {T} M {M}", flush=True)
@@ -68,6 +74,8 @@ def test_forward_and_adjoint_match_oracle(name, T, M):
     x0[:, :prob.npos] += rng.uniform(-0.3, 0.3, (n, prob.npos)).astype(np.float32)
     if name == "uni2":
         x0[:, 3:] = rng.uniform(-0.3, 0.3, (n, 2)).astype(np.float32)
+    if name in ("acrobot", "cartpole"):
+        x0[:, 2:] = rng.uniform(-1.0, 1.0, (n, 2)).astype(np.float32)
     Ud, x0d = torch.from_numpy(U).cuda(), torch.from_numpy(x0).cuda()
     J, ckpt = ref.forward(x0d, Ud)
     gU = ref.backward(Ud, ckpt, torch.ones(n, device="cuda"))
@@ -90,7 +98,7 @@ def test_forward_and_adjoint_match_oracle(name, T, M):
     ref.close()
 
 
-@pytest.mark.parametrize("name", ["dubins", "uni1", "uni2"])
+@pytest.mark.parametrize("name", ["dubins", "uni1", "uni2", "acrobot", "cartpole"])
 def test_extracted_path_is_feasible(name):
     prob = W.MORE_CONFIGS[name](max_iters_per_round=400)
     print(f"case path {name}", flush=True)
@@ -113,14 +121,15 @@ def test_extracted_path_is_feasible(name):
     plan.close()
 
 
-def test_batch_of_all_seven_systems_equals_single_plans():
+def test_batch_of_all_nine_systems_equals_single_plans():
     probs = [W.config_c1(seed=1, B=512, A=8), W.config_c2(seed=1, B=512, A=8),
              W.config_c3(seed=1, B=512, A=16), W.config_c4(seed=1, B=256, A=16),
              W.config_dubins(seed=1, B=512, A=8), W.config_uni1(seed=1, B=512, A=8),
-             W.config_uni2(seed=1, B=512, A=8), W.config_uni1(seed=2, B=256, A=4)]
+             W.config_uni2(seed=1, B=512, A=8), W.config_uni1(seed=2, B=256, A=4),
+             W.config_acrobot(seed=1, B=512, A=8), W.config_cartpole(seed=1, B=256, A=4)]
     probs = [p.replace(max_iters_per_round=30, n_cap=min(p.n_cap, 30000), qid=q)
              for q, p in enumerate(probs)]
-    print("case batch of the seven systems, teams auto, 2 rounds", flush=True)
+    print("case batch of the nine systems, teams auto, 2 rounds", flush=True)
     bp = pakr.BatchPlan(probs, lanes=1, teams=0)
     bp.replan(max_rounds=2)
     for q, prob in enumerate(probs):
