@@ -40,7 +40,8 @@ def flops_per_expansion(prob):
     """
     from paper_2607_03987_amd import workloads as W
     d, P = prob.d, prob.npos
-    f_eval = {W.DI2: 0, W.DI3: 0, W.CAR: 8, W.QUAD: 84}[prob.system]
+    f_eval = {W.DI2: 0, W.DI3: 0, W.CAR: 8, W.QUAD: 84, W.DUBINS: 8, W.UNI1: 4, W.UNI2: 4,
+              W.ACROBOT: 38, W.CARTPOLE: 6}[prob.system]
     nb, ns = prob.box_c.shape[0], prob.sph_r.shape[0]
     speed = 2 * P if float(prob.vnorm_max) > 0 else 0
     step = 12 * d + 4 * f_eval + speed + P * nb + 3 * P * ns
@@ -240,6 +241,49 @@ def refinement_leg(torch, pakr, refine, W, budget_ms, n_multi):
     return out
 
 
+def other_systems_leg(torch, pakr, W, budget_ms, seeds):
+    """The paper's other analytic systems (Dubins airplane, unicycles 1 and 2,
+    acrobot and cart-pole swing-ups) at their default workloads: each seed is
+    one single-query AO-x plan with a device-clock budget; expansions/s from the
+    kernel's own event timing, the median time to the first solution, and the
+    planner kernel's achieved FP32 rate against the vector peak."""
+    out = {}
+    stream = torch.cuda.current_stream()
+    for name, mk in W.MORE_CONFIGS.items():
+        w = pakr.Plan(mk(seed=10_000))
+        w.replan(budget_ms=min(budget_ms, 20.0))
+        torch.cuda.synchronize()
+        w.close()
+        exp = pairs = 0
+        ms, t_first = [], []
+        for sd in range(seeds):
+            prob = mk(seed=sd)
+            pl = pakr.Plan(prob)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            pl.replan(budget_ms=budget_ms)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            st, sols = pl.status(), pl.solutions()
+            ms.append(e0.elapsed_time(e1))
+            exp += st["expansions"]
+            pairs += st["nn_pairs"]
+            if sols:
+                t_first.append(sols[0]["t_ms"])
+            pl.close()
+        prob = mk(seed=0)
+        flops = exp * flops_per_expansion(prob) + pairs * nn_flops_per_pair(prob)
+        tf = flops / (sum(ms) / 1e3) / 1e12
+        out[name] = {"expansions_per_s": exp / (sum(ms) / 1e3),
+                     "time_to_first_ms_median": statistics.median(t_first) if t_first else None,
+                     "solved": f"{len(t_first)}/{seeds}", "B": prob.B, "A": prob.A, "T": prob.T,
+                     "kernel_ms_mean": statistics.mean(ms),
+                     "roofline": {"bound": "alu", "achieved": tf,
+                                  "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                  "frac": tf / FP32_VECTOR_PEAK_TFLOPS}}
+    return out
+
+
 def cpu_baseline(prob, seconds):
     """Time the FP64 reference (single thread) on the same query for ~`seconds`."""
     import oracle
@@ -273,6 +317,9 @@ def main():
     ap.add_argument("--batch-iters-per-round", type=int, default=50)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-refine", action="store_true")
+    ap.add_argument("--no-other-systems", action="store_true")
+    ap.add_argument("--other-systems-ms", type=float, default=100.0)
+    ap.add_argument("--other-systems-seeds", type=int, default=3)
     ap.add_argument("--refine-budget-ms", type=float, default=500.0)
     ap.add_argument("--refine-paths", type=int, default=256)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -395,6 +442,7 @@ def main():
         "cpu_baseline": None,
         "batched": None,
         "refinement": None,
+        "other_systems": None,
     }
     for p in plans:
         p.close()
@@ -406,6 +454,9 @@ def main():
     if not args.no_refine:
         out["refinement"] = refinement_leg(torch, pakr, refine, W, args.refine_budget_ms,
                                            args.refine_paths)
+    if not args.no_other_systems:
+        out["other_systems"] = other_systems_leg(torch, pakr, W, args.other_systems_ms,
+                                                 args.other_systems_seeds)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W.config_c2(seed=0), args.cpu_seconds)
     print(json.dumps(out), flush=True)
