@@ -61,6 +61,15 @@ __device__ __forceinline__ unsigned long long pack_key(float v, uint32_t idx) {
   return ((unsigned long long)__float_as_uint(v) << 32) | (unsigned long long)idx;
 }
 
+// A store that goes through to device-coherent memory (an agent-scope relaxed
+// atomic store: the L2 keeps no dirty copy).  Used for the NN partial keys,
+// which every workgroup writes just before a grid barrier: the barrier's
+// release (an L2 write-back on this multi-XCD GPU) then has less to flush.
+template <typename T>
+__device__ __forceinline__ void store_through(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Grid-wide barrier with a bounded wait.  The last workgroup collects the
 // arrival flags and publishes a release word (generation << 1 | failed).  Returns
 // false if any wait timed out; every workgroup then leaves the kernel.
@@ -405,7 +414,8 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
           }
         }
         if (direct) {
-          if (tid < kc) a.partial[(size_t)b * K + base + tid] = pack_key(bd[0], (uint32_t)bi[0]);
+          if (tid < kc)
+            store_through(&a.partial[(size_t)b * K + base + tid], pack_key(bd[0], (uint32_t)bi[0]));
         } else {
 #pragma unroll
           for (int qq = 0; qq < QT; ++qq) {
@@ -417,7 +427,8 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
             }
           }
           __syncthreads();
-          for (int k = tid; k < kc; k += NT) a.partial[(size_t)b * K + base + k] = s_key[k];
+          for (int k = tid; k < kc; k += NT)
+            store_through(&a.partial[(size_t)b * K + base + k], s_key[k]);
         }
       }
     }
