@@ -327,8 +327,8 @@ def main():
                          "kernel against which HBM counters are scaled)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the planner has no "
-              "multi-GPU path in this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the planner runs "
+              "on a single GPU and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import torch
