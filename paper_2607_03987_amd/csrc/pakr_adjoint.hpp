@@ -319,51 +319,47 @@ __device__ __forceinline__ void dynamics_vjp(const DevProblem& P, const float* x
   }
 }
 
-// Trigonometric values of a state that every lane of the wave holds: the
-// quadrotor's three angles (the Dubins airplane's two) are evaluated on lanes
-// 0-2 (0-1) at once and broadcast (one sincos on the serial chain instead of
-// three; same values).
-__device__ __forceinline__ float lane_value(float v, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+// Trigonometric values for the refinement's rollouts, from the hardware sine
+// and cosine (v_sin_f32 / v_cos_f32 after scaling to revolutions; absolute
+// error about 1e-6 at these angles) rather than the correctly rounded
+// library sincos: the rollout is one serial chain per path, and its length
+// sets the refinement's latency.  The objective's f and its VJP take the same
+// values, so the gradient is exact for the objective as evaluated; the
+// planner's own check of a refined path (k_check_path) integrates with the
+// planner's f.
+__device__ __forceinline__ void fast_sincos(float a, float* s, float* c) {
+  *s = __sinf(a);
+  *c = __cosf(a);
 }
 
 template <int SYS>
-__device__ __forceinline__ Trig wave_trig(const float* x, int lane) {
-  if constexpr (SYS == PAKR_DUBINS || SYS == PAKR_ACROBOT) {
-    // two angles: lane 0 and lane 1 (Dubins yaw and pitch, acrobot joints)
-    constexpr int A0 = SYS == PAKR_DUBINS ? 3 : 0;
-    const float ang = lane == 0 ? x[A0] : x[A0 + 1];
-    float sv, cv;
-    sincosf(ang, &sv, &cv);
-    Trig g;
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      g.s[k] = lane_value(sv, k);
-      g.c[k] = lane_value(cv, k);
-    }
-    if constexpr (SYS == PAKR_ACROBOT) {  // angle sum, as trig_of takes it
-      g.s[2] = g.s[0] * g.c[1] + g.c[0] * g.s[1];
-      g.c[2] = g.c[0] * g.c[1] - g.s[0] * g.s[1];
-    } else {
-      g.s[2] = g.c[2] = 0.0f;
-    }
-    g.t = 0.0f;
-    return g;
+__device__ __forceinline__ Trig wave_trig(const float* x, int /*lane*/) {
+  Trig g;
+  g.s[0] = g.s[1] = g.s[2] = 0.0f;
+  g.c[0] = g.c[1] = g.c[2] = 0.0f;
+  g.t = 0.0f;
+  if constexpr (SYS == PAKR_CAR) {
+    fast_sincos(x[2], &g.s[0], &g.c[0]);
+    float sp, cp;
+    fast_sincos(x[4], &sp, &cp);
+    g.t = sp / cp;
   } else if constexpr (SYS == PAKR_QUAD) {
-    const float ang = lane == 0 ? x[3] : (lane == 1 ? x[4] : x[5]);
-    float sv, cv;
-    sincosf(ang, &sv, &cv);
-    Trig g;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      g.s[k] = lane_value(sv, k);
-      g.c[k] = lane_value(cv, k);
-    }
-    g.t = 0.0f;
-    return g;
-  } else {
-    return trig_of<SYS>(x);
+    for (int k = 0; k < 3; ++k) fast_sincos(x[3 + k], &g.s[k], &g.c[k]);
+  } else if constexpr (SYS == PAKR_DUBINS) {
+    fast_sincos(x[3], &g.s[0], &g.c[0]);
+    fast_sincos(x[4], &g.s[1], &g.c[1]);
+  } else if constexpr (SYS == PAKR_UNI1 || SYS == PAKR_UNI2) {
+    fast_sincos(x[2], &g.s[0], &g.c[0]);
+  } else if constexpr (SYS == PAKR_CARTPOLE) {
+    fast_sincos(x[1], &g.s[0], &g.c[0]);
+  } else if constexpr (SYS == PAKR_ACROBOT) {
+    fast_sincos(x[0], &g.s[0], &g.c[0]);
+    fast_sincos(x[1], &g.s[1], &g.c[1]);
+    g.s[2] = g.s[0] * g.c[1] + g.c[0] * g.s[1];  // angle sum
+    g.c[2] = g.c[0] * g.c[1] - g.s[0] * g.s[1];
   }
+  return g;
 }
 
 // One RK4 step (as the planner takes it) on a state the whole wave holds.
