@@ -133,7 +133,7 @@ Layout make_layout(int d, int m, const pakr_params& p, int G, int obs_floats, in
   L.parents = take(sizeof(int) * N);
   L.costs = take(sizeof(float) * N);
   L.obs = take(sizeof(float) * (size_t)std::max(obs_floats, 1));
-  L.partial = take(sizeof(unsigned long long) * (size_t)G * K);
+  L.partial = take(sizeof(unsigned long long) * 2 * (size_t)K);  // two NN key buffers
   L.stg = take(sizeof(float) * S * (size_t)(d + m + 4));
   L.counts = take(sizeof(int) * GR);
   L.goalmin = take(sizeof(unsigned long long) * GR);

@@ -62,9 +62,10 @@ __device__ __forceinline__ unsigned long long pack_key(float v, uint32_t idx) {
 }
 
 // A store that goes through to device-coherent memory (an agent-scope relaxed
-// atomic store: the L2 keeps no dirty copy).  Used for the NN partial keys,
-// which every workgroup writes just before a grid barrier: the barrier's
-// release (an L2 write-back on this multi-XCD GPU) then has less to flush.
+// atomic store: the L2 keeps no dirty copy), so a grid barrier's release (an
+// L2 write-back on this multi-XCD GPU) has less to flush.  Used to clear the
+// NN key buffers, which the workgroups then fold their minima into with
+// device-scope atomics (also performed past the L2).
 template <typename T>
 __device__ __forceinline__ void store_through(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -291,7 +292,12 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
     bk.c_exp = bk.c_ins = bk.c_nn = 0;
     bk.c_sol = 0;
   }
-  __syncthreads();
+  // both NN key buffers start cleared
+  for (int k = b * NT + tid; k < 2 * K; k += G * NT) store_through(&a.partial[k], ~0ull);
+  if (!grid_barrier(a, gen, &s_fail, b, G)) {
+    if (tid == 0) __hip_atomic_store(&a.hdr->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
 
   while (true) {
     if (a.max_iters > 0 && it_done >= a.max_iters) { status |= PAKR_S_ITERS_DONE; break; }
@@ -300,6 +306,10 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
                                                                  : nullptr;
     const int ntiles = (n + TILE - 1) / TILE;
     const int G_act = min(G, ntiles);
+    // this iteration's NN keys: every scanning workgroup folds its minima in
+    // by device-scope atomic min; two buffers alternate, each cleared during
+    // the insertion phase of the iteration that consumed it
+    unsigned long long* const nnk = a.partial + (size_t)(it_done & 1) * K;
     if (keeper) bk.tk_mark = wall_clock64();
 
     // ---------------- phase 1: targets + nearest neighbour -----------------
@@ -415,7 +425,7 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
         }
         if (direct) {
           if (tid < kc)
-            store_through(&a.partial[(size_t)b * K + base + tid], pack_key(bd[0], (uint32_t)bi[0]));
+            atomicMin(&nnk[base + tid], pack_key(bd[0], (uint32_t)bi[0]));
         } else {
 #pragma unroll
           for (int qq = 0; qq < QT; ++qq) {
@@ -428,7 +438,7 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
           }
           __syncthreads();
           for (int k = tid; k < kc; k += NT)
-            store_through(&a.partial[(size_t)b * K + base + k], s_key[k]);
+            atomicMin(&nnk[base + k], s_key[k]);
         }
       }
     }
@@ -463,37 +473,7 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
       for (int i = tid; i < nql; i += NT) s_best[i] = ~0ull;
       if (tid == 0) s_goal = ~0ull;
       __syncthreads();
-      if (NT % nql == 0) {
-        // each thread folds a strided set of workgroups' keys for one target
-        // in registers (independent loads in flight), then one LDS atomic
-        const int qi = tid % nql, stride = NT / nql;
-        const unsigned long long* src_p = a.partial + k0 + qi;
-        unsigned long long m0 = ~0ull, m1 = ~0ull;
-        int src = tid / nql;
-        for (; src + 7 * stride < G_act; src += 8 * stride) {
-          unsigned long long v[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) v[u] = src_p[(size_t)(src + u * stride) * K];
-#pragma unroll
-          for (int u = 0; u < 8; u += 2) {
-            m0 = v[u] < m0 ? v[u] : m0;
-            m1 = v[u + 1] < m1 ? v[u + 1] : m1;
-          }
-        }
-        for (; src < G_act; src += stride) {
-          const unsigned long long v = src_p[(size_t)src * K];
-          m0 = v < m0 ? v : m0;
-        }
-        m0 = m1 < m0 ? m1 : m0;
-        if (m0 != ~0ull) atomicMin(&s_best[qi], m0);
-      } else {
-        const int tot = nql * G_act;
-        for (int idx = tid; idx < tot; idx += NT) {
-          const int qi = idx % nql;
-          const int src = idx / nql;
-          atomicMin(&s_best[qi], a.partial[(size_t)src * K + k0 + qi]);
-        }
-      }
+      for (int i = tid; i < nql; i += NT) s_best[i] = nnk[k0 + i];
       __syncthreads();
       mark(2);
 
@@ -608,6 +588,7 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
     }
 
     mark(4);
+    for (int k = b * NT + tid; k < K; k += G * NT) store_through(&nnk[k], ~0ull);
 
     // ---------------- phase 3: insert + goal + round bookkeeping ----------
     for (int w = tid; w < GR; w += NT) s_cnt[w] = a.counts[w];
