@@ -22,7 +22,7 @@ constexpr int DEFAULT_PATH_EDGES = 4096;
 thread_local std::string g_init_error;
 
 struct Layout {
-  size_t hdr, bar, sols, pstates, pactions, states, actions, parents, costs, obs, partial, stg,
+  size_t hdr, bar, sols, pstates, pactions, states, actions, parents, costs, obs, nn_keys, stg,
       counts, goalmin, total;
 };
 
@@ -133,7 +133,7 @@ Layout make_layout(int d, int m, const pakr_params& p, int G, int obs_floats, in
   L.parents = take(sizeof(int) * N);
   L.costs = take(sizeof(float) * N);
   L.obs = take(sizeof(float) * (size_t)std::max(obs_floats, 1));
-  L.partial = take(sizeof(unsigned long long) * 2 * (size_t)K);  // two NN key buffers
+  L.nn_keys = take(sizeof(unsigned long long) * 2 * (size_t)K);  // two NN key buffers
   L.stg = take(sizeof(float) * S * (size_t)(d + m + 4));
   L.counts = take(sizeof(int) * GR);
   L.goalmin = take(sizeof(unsigned long long) * GR);
@@ -417,7 +417,7 @@ KArgs make_args(const DevProblem& Q, char* base, const Layout& L) {
   a.parents = reinterpret_cast<int*>(base + L.parents);
   a.costs = reinterpret_cast<float*>(base + L.costs);
   a.obs = reinterpret_cast<const float*>(base + L.obs);
-  a.partial = reinterpret_cast<unsigned long long*>(base + L.partial);
+  a.nn_keys = reinterpret_cast<unsigned long long*>(base + L.nn_keys);
   a.stg = reinterpret_cast<float*>(base + L.stg);
   a.counts = reinterpret_cast<int*>(base + L.counts);
   a.goalmin = reinterpret_cast<unsigned long long*>(base + L.goalmin);

@@ -4,16 +4,17 @@
 // device with no host round-trip.  Each inner iteration has three phases
 // separated by two grid barriers:
 //
-//   1. SampleStates + NearestNeighbor.  Every workgroup draws all K targets
-//      (Philox, registers) and scans the tree tiles it owns -- tile t (64
-//      nodes) belongs to workgroup t mod G -- staging each tile through LDS and
-//      keeping a per-target (distance, index) minimum.  The partial minima go
-//      to HBM as packed u64 keys [G][K].
-//   2. SampleControls + Propagate + CollisionFree + prune.  Workgroup w < G_roll
-//      owns candidates j in [256w, 256w+256): it reduces the partial minima of
-//      its parents, rolls each candidate out with RK4 (one lane per candidate,
-//      obstacles in LDS), and compacts the survivors in candidate order into a
-//      staging area with a wave ballot + prefix count.
+//   1. SampleStates + NearestNeighbor.  Every workgroup draws the K targets
+//      (Philox), stages them in LDS, and scans the tree tiles it owns -- tile t
+//      (64 nodes) belongs to workgroup t mod G -- staging each tile through
+//      LDS; threads hold several targets and scan a slice of each tile.  Each
+//      workgroup folds its per-target (distance, index) minima, packed into
+//      u64 keys, into the iteration's key buffer with a device-scope atomic min.
+//   2. SampleControls + Propagate + CollisionFree + prune.  Rollout workgroup w
+//      owns a chunk of consecutive candidates j (L lanes per candidate): it
+//      reads its parents' keys, rolls each candidate out with RK4 (the L lanes
+//      share the obstacle tests, obstacles in LDS), and compacts the survivors
+//      in candidate order into a staging area with a wave ballot + prefix count.
 //   3. Insert + bookkeeping.  All workgroups read the survivor counts, take an
 //      exclusive prefix, and copy the survivors that land in their own tiles
 //      from staging into the tree (so the next phase 1 reads only slots its
@@ -43,7 +44,7 @@ struct KArgs {
   int* parents;                     // [n_cap]
   float* costs;                     // [n_cap]
   const float* obs;                 // packed obstacles (see any_obstacle_hit)
-  unsigned long long* partial;      // [G][K] packed (d2 bits << 32 | node)
+  unsigned long long* nn_keys;      // [2][K] packed (d2 bits << 32 | node), alternate iterations
   float* stg;                       // survivor staging, S = G_roll*cpb entries
   int* counts;                      // [G_roll] survivors per rollout workgroup
   unsigned long long* goalmin;      // [G_roll] packed (cost bits << 32 | j)
@@ -293,7 +294,7 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
     bk.c_sol = 0;
   }
   // both NN key buffers start cleared
-  for (int k = b * NT + tid; k < 2 * K; k += G * NT) store_through(&a.partial[k], ~0ull);
+  for (int k = b * NT + tid; k < 2 * K; k += G * NT) store_through(&a.nn_keys[k], ~0ull);
   if (!grid_barrier(a, gen, &s_fail, b, G)) {
     if (tid == 0) __hip_atomic_store(&a.hdr->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return;
@@ -309,7 +310,7 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
     // this iteration's NN keys: every scanning workgroup folds its minima in
     // by device-scope atomic min; two buffers alternate, each cleared during
     // the insertion phase of the iteration that consumed it
-    unsigned long long* const nnk = a.partial + (size_t)(it_done & 1) * K;
+    unsigned long long* const nnk = a.nn_keys + (size_t)(it_done & 1) * K;
     if (keeper) bk.tk_mark = wall_clock64();
 
     // ---------------- phase 1: targets + nearest neighbour -----------------
