@@ -72,8 +72,9 @@ __device__ __forceinline__ void store_through(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Grid-wide barrier with a bounded wait.  The last workgroup collects the
-// arrival flags and publishes a release word (generation << 1 | failed).  Returns
+// Grid-wide barrier with a bounded wait.  Workgroup 0 collects the other
+// workgroups' arrival flags and publishes a release word (generation << 1 |
+// failed).  Returns
 // false if any wait timed out; every workgroup then leaves the kernel.
 //
 // Every workgroup makes its own writes visible (agent-scope release: L2
@@ -87,11 +88,13 @@ __device__ __forceinline__ bool grid_barrier(const KArgs& a, uint32_t& gen, int*
   __syncthreads();
   if (G == 1) return true;
   const uint32_t target = gen & 0x7fffffffu;
-  const int master = G - 1;  // owns no more NN tiles than any other workgroup
+  // workgroup 0 owns the most NN tiles and the first rollout chunk, so it is
+  // usually the last to arrive and finds the other flags already raised
+  const int master = 0;
   if (wg == master) {
     if (threadIdx.x == 0) *s_fail = 0;
     __syncthreads();
-    for (int i = threadIdx.x; i < master; i += NT) {
+    for (int i = threadIdx.x + 1; i < G; i += NT) {
       long long limit = 0;
       while (__hip_atomic_load(&a.bar_flags[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) !=
              target) {
