@@ -53,6 +53,22 @@ def test_step_parity_no_obstacles_and_small_grid():
     step_parity(prob, 8, grid=8, log=_log)
 
 
+@pytest.mark.parametrize("grid", [1, 2, 3])
+def test_step_parity_tiny_grids(grid):
+    # one workgroup (no grid barrier at all), two (each owns every other tile),
+    # three (ragged tile ownership); the NN key buffers alternate every iteration
+    prob = W.config_c2(B=512, A=8, n_cap=20000)
+    print(f"case c2 grid {grid}", flush=True)
+    step_parity(prob, 7, grid=grid, log=_log)
+
+
+def test_step_parity_targets_in_several_chunks():
+    # K = 2048 targets: the NN scan stages them in LDS in two chunks of 1024
+    prob = W.config_c1(B=4096, A=2, n_cap=20000)
+    print("case c1 K 2048", flush=True)
+    step_parity(prob, 5, log=_log)
+
+
 @pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16])
 @pytest.mark.parametrize("cfg,kw", [("c2", dict(B=1024, A=8, n_cap=30000)),
                                     ("c4", dict(B=256, A=16, n_cap=30000))])
