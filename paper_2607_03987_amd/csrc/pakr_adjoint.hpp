@@ -47,18 +47,23 @@ struct TrajArgs {
 // sigmoid(beta z).  A term with beta z < SP_CUT is taken as zero (its value is
 // below e^-30 / beta), so inactive terms cost a compare: for the state-bound
 // terms, which every lane evaluates on the same state, the branch is uniform.
+// The hardware exp2 / log2 (v_exp_f32, v_log_f32, a few ulp) stand in for the
+// library exp / log1p: log(1 + e) loses e's last bits only when e is below the
+// float epsilon, i.e. for terms under 1e-7 / beta, and these penalties sit on
+// the rollout's serial chain.
 constexpr float SP_CUT = -30.0f;
 
 __device__ __forceinline__ float softplus_b(float z, const RefineParams& R) {
   const float bz = R.beta * z;
   if (bz < SP_CUT) return 0.0f;
-  return bz > 0.0f ? z + log1pf(expf(-bz)) * R.inv_beta : log1pf(expf(bz)) * R.inv_beta;
+  return bz > 0.0f ? z + __logf(1.0f + __expf(-bz)) * R.inv_beta
+                    : __logf(1.0f + __expf(bz)) * R.inv_beta;
 }
 
 __device__ __forceinline__ float sigmoid_b(float z, const RefineParams& R) {
   const float bz = R.beta * z;
   if (bz < SP_CUT) return 0.0f;
-  return 1.0f / (1.0f + expf(-bz));
+  return __frcp_rn(1.0f + __expf(-bz));
 }
 
 __device__ __forceinline__ float wave_sum(float v) {
