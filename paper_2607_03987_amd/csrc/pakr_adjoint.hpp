@@ -50,7 +50,8 @@ struct TrajArgs {
 // The hardware exp2 / log2 (v_exp_f32, v_log_f32, a few ulp) stand in for the
 // library exp / log1p: log(1 + e) loses e's last bits only when e is below the
 // float epsilon, i.e. for terms under 1e-7 / beta, and these penalties sit on
-// the rollout's serial chain.
+// the rollout's serial chain.  For the same reason the signed distances use
+// the hardware square root and reciprocal (v_sqrt_f32, v_rcp_f32, 1 ulp).
 constexpr float SP_CUT = -30.0f;
 
 __device__ __forceinline__ float softplus_b(float z, const RefineParams& R) {
@@ -96,7 +97,7 @@ __device__ __forceinline__ float obstacle_penalty(const DevProblem& P, const Ref
       }
     }
     // signed distance to the box: outside part plus (inside) the largest face gap
-    const float so = outside > 0.0f ? sqrtf(outside) : 0.0f;
+    const float so = outside > 0.0f ? __builtin_amdgcn_sqrtf(outside) : 0.0f;
     const float sd = so + (inner < 0.0f ? inner : 0.0f);
     pen += softplus_b(R.delta - sd, R);
     if (grad) {
@@ -104,7 +105,7 @@ __device__ __forceinline__ float obstacle_penalty(const DevProblem& P, const Ref
 #pragma unroll
       for (int c = 0; c < NP; ++c) {
         float dq = 0.0f;
-        if (so > 0.0f && q[c] > 0.0f) dq += q[c] / so;
+        if (so > 0.0f && q[c] > 0.0f) dq += q[c] * __builtin_amdgcn_rcpf(so);
         if (inner < 0.0f && c == arg) dq += 1.0f;
         grad[c] += dsd * dq * sg[c];
       }
@@ -119,11 +120,11 @@ __device__ __forceinline__ float obstacle_penalty(const DevProblem& P, const Ref
       e[c] = x[c] - o[c];
       r2 += e[c] * e[c];
     }
-    const float dist = sqrtf(r2);
-    const float sd = dist - sqrtf(o[NP]);  // the record holds r^2
+    const float dist = __builtin_amdgcn_sqrtf(r2);
+    const float sd = dist - __builtin_amdgcn_sqrtf(o[NP]);  // the record holds r^2
     pen += softplus_b(R.delta - sd, R);
     if (grad && dist > 0.0f) {
-      const float dsd = -sigmoid_b(R.delta - sd, R) / dist;
+      const float dsd = -sigmoid_b(R.delta - sd, R) * __builtin_amdgcn_rcpf(dist);
 #pragma unroll
       for (int c = 0; c < NP; ++c) grad[c] += dsd * e[c];
     }
@@ -159,10 +160,10 @@ __device__ __forceinline__ float bound_penalty(const DevProblem& P, const Refine
       float v2 = 0.0f;
 #pragma unroll
       for (int c = 0; c < NP; ++c) v2 += x[NP + c] * x[NP + c];
-      const float vn = sqrtf(v2);
+      const float vn = __builtin_amdgcn_sqrtf(v2);
       pen += softplus_b(vn - P.vnorm_max, R);
       if (grad && vn > 0.0f) {
-        const float g = sigmoid_b(vn - P.vnorm_max, R) / vn;
+        const float g = sigmoid_b(vn - P.vnorm_max, R) * __builtin_amdgcn_rcpf(vn);
 #pragma unroll
         for (int c = 0; c < NP; ++c) grad[NP + c] += g * x[NP + c];
       }
