@@ -56,8 +56,7 @@ struct DevHeader {
   int best_edges, best_node, pad0, pad1;
   float best_cost, pad2, pad3, pad4;
   uint32_t release;                          // barrier release word
-  int stop[2];                               // per-iteration stop decision (parity)
-  int pad5;
+  int pad5[3];
   long long ticks[8];                        // per-step device time of the last call
 };
 

@@ -73,9 +73,11 @@ __device__ __forceinline__ void store_through(T* p, T v) {
 }
 
 // Grid-wide barrier with a bounded wait.  Workgroup 0 collects the other
-// workgroups' arrival flags and publishes a release word (generation << 1 |
-// failed).  Returns
-// false if any wait timed out; every workgroup then leaves the kernel.
+// workgroups' arrival flags and publishes a release word (generation << 3 |
+// note << 1 | failed), where note (0..3) is a value workgroup 0's thread 0
+// left in *s_note before the barrier; every workgroup finds it there after the
+// barrier, with no extra memory round trip.  Returns false if any wait timed
+// out; every workgroup then leaves the kernel.
 //
 // Every workgroup makes its own writes visible (agent-scope release: L2
 // write-back) before raising its flag, so the collecting workgroup publishes
@@ -83,11 +85,11 @@ __device__ __forceinline__ void store_through(T* p, T v) {
 // (L2 invalidate) for the reads that follow.  One wave per workgroup runs the
 // acquire; the workgroup barrier after it orders the other waves' reads.
 __device__ __forceinline__ bool grid_barrier(const KArgs& a, uint32_t& gen, int* s_fail, int wg,
-                                             int G) {
+                                             int G, int* s_note = nullptr) {
   ++gen;
   __syncthreads();
   if (G == 1) return true;
-  const uint32_t target = gen & 0x7fffffffu;
+  const uint32_t target = gen & 0x1fffffffu;
   // workgroup 0 owns the most NN tiles and the first rollout chunk, so it is
   // usually the last to arrive and finds the other flags already raised
   const int master = 0;
@@ -111,7 +113,8 @@ __device__ __forceinline__ bool grid_barrier(const KArgs& a, uint32_t& gen, int*
     __syncthreads();
     if (threadIdx.x == 0) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      __hip_atomic_store(&a.hdr->release, (target << 1) | (uint32_t)(*s_fail != 0),
+      const uint32_t note = s_note != nullptr ? (uint32_t)*s_note & 3u : 0u;
+      __hip_atomic_store(&a.hdr->release, (target << 3) | (note << 1) | (uint32_t)(*s_fail != 0),
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
@@ -123,8 +126,9 @@ __device__ __forceinline__ bool grid_barrier(const KArgs& a, uint32_t& gen, int*
     while (true) {
       const uint32_t v = __hip_atomic_load(&a.hdr->release, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
-      if ((v >> 1) == target) {
+      if ((v >> 3) == target) {
         *s_fail = (int)(v & 1u);
+        if (s_note != nullptr) *s_note = (int)((v >> 1) & 3u);
         break;
       }
       if (wall_clock64() > limit) {
@@ -447,20 +451,16 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
       }
     }
     mark(0);
-    if (b == 0 && tid == 0) {
+    // workgroup 0 decides whether the call stops here (1: budget spent,
+    // 2: guard time exceeded) and the barrier's release word carries it
+    if (keeper) {
       const long long now = wall_clock64();
-      const int stop = now >= bk.deadline ? 1 : (now >= bk.guard ? 2 : 0);
-      __hip_atomic_store(&a.hdr->stop[it_done & 1], stop, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
+      s_misc[0] = now >= bk.deadline ? 1 : (now >= bk.guard ? 2 : 0);
     }
-    if (!grid_barrier(a, gen, &s_fail, b, G)) {
+    if (!grid_barrier(a, gen, &s_fail, b, G, &s_misc[0])) {
       if (tid == 0) __hip_atomic_store(&a.hdr->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return;
     }
-    if (tid == 0)
-      s_misc[0] = __hip_atomic_load(&a.hdr->stop[it_done & 1], __ATOMIC_RELAXED,
-                                    __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
     if (s_misc[0] != 0) {
       status |= (s_misc[0] == 1) ? PAKR_S_BUDGET_EXPIRED : PAKR_S_DEVICE_ERROR;
       break;
@@ -595,7 +595,15 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
     for (int k = b * NT + tid; k < K; k += G * NT) store_through(&nnk[k], ~0ull);
 
     // ---------------- phase 3: insert + goal + round bookkeeping ----------
-    for (int w = tid; w < GR; w += NT) s_cnt[w] = a.counts[w];
+    // The goal keys load together with the counts, so that their round trip
+    // overlaps the scan and the copy; their minimum is the iteration's goal
+    // candidate unless the tree fills up part-way through the survivors.
+    unsigned long long gall = ~0ull;
+    for (int w = tid; w < GR; w += NT) {
+      s_cnt[w] = a.counts[w];
+      const unsigned long long kk = a.goalmin[w];
+      gall = kk < gall ? kk : gall;
+    }
     __syncthreads();
     block_exclusive_scan(s_cnt, s_off, GR, s_wave);
     const int survivors = s_off[GR];
@@ -631,8 +639,8 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
       }
     }
     // cheapest inserted goal candidate, ties to the lowest j
-    unsigned long long key = ~0ull;
-    for (int w = tid; w < GR; w += NT) {
+    unsigned long long key = n_ins == survivors ? gall : ~0ull;
+    for (int w = n_ins == survivors ? GR : tid; w < GR; w += NT) {
       const int off = s_off[w], cnt = s_cnt[w];
       if (off + cnt <= n_ins) {
         const unsigned long long kk = a.goalmin[w];
