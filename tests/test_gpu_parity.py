@@ -148,3 +148,33 @@ def test_extracted_path_is_feasible():
     sols = plan.solutions()
     assert sols[-1]["cost"] == pytest.approx(cost)
     assert all(b["cost"] < a["cost"] for a, b in zip(sols, sols[1:]))
+
+
+@pytest.mark.parametrize("grid", [0, 3, 1])
+def test_budget_stop_ends_every_workgroup_at_one_iteration(grid):
+    """Workgroup 0 takes the budget decision and every workgroup leaves at the
+    same iteration: the tree then equals that of a call capped at the same
+    number of iterations, and planning resumes from it."""
+    prob = W.config_c2(B=512, A=8, n_cap=200000)
+    print(f"case c2 budget 15 ms grid {grid}", flush=True)
+    a = pakr.Plan(prob, grid=grid)
+    a.replan(budget_ms=15.0)
+    st = a.status()
+    assert st["status"] & pakr.S_BUDGET_EXPIRED, st["status"]
+    assert st["call_iters"] > 0
+    assert 15.0 <= st["call_ms"] <= 15.0 + 10.0, st["call_ms"]
+    b = pakr.Plan(prob, grid=grid)
+    b.replan(max_iters=st["call_iters"])
+    sb = b.status()
+    assert sb["status"] & pakr.S_ITERS_DONE and not sb["status"] & pakr.S_BUDGET_EXPIRED
+    for key in ("total_iters", "n_nodes", "round", "iter", "insertions", "n_solutions"):
+        assert st[key] == sb[key], (key, st[key], sb[key])
+    for x, y in zip(a.copy_tree(), b.copy_tree()):
+        np.testing.assert_array_equal(x, y)
+    ta = a.expand(4, trace=True)
+    tb = b.expand(4, trace=True)
+    for x, y in zip(ta, tb):
+        for key in ("parents", "slots", "flags"):
+            np.testing.assert_array_equal(x[key], y[key])
+    a.close()
+    b.close()
