@@ -284,6 +284,43 @@ def other_systems_leg(torch, pakr, W, budget_ms, seeds):
     return out
 
 
+def saturating_rollout_leg(torch, pakr, W, iters, B=65536, A=16):
+    """The rollout step at the largest batch one launch takes (B = 65536
+    quadrotor candidates, 12D, T 40, 50 spheres): every iteration is capped at
+    one per round, so each starts a new round from the root, the NN scan covers
+    one node and the kernel time is the rollout, validity test and insertion of
+    B candidates.  FP32 rate from the kernel's event timing, as for the planner
+    legs."""
+    prob = W.config_c4(B=B, A=A, n_cap=1 << 20, max_iters_per_round=1)
+    stream = torch.cuda.current_stream()
+    pl = pakr.Plan(prob)
+    pl.expand(2)
+    torch.cuda.synchronize()
+    st0 = pl.status()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    pl.expand(iters)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    st = pl.status()
+    ms = e0.elapsed_time(e1)
+    exp = st["expansions"] - st0["expansions"]
+    pairs = st["nn_pairs"] - st0["nn_pairs"]
+    ins = st["insertions"] - st0["insertions"]
+    flops = exp * flops_per_expansion(prob) + pairs * nn_flops_per_pair(prob)
+    tf = flops / (ms / 1e3) / 1e12
+    out = {"workload": f"12D quadrotor, [0,10]^3, 50 spheres r U(0.3,1.2), B {B}, A {A}, T 40, "
+                       f"dt 0.02; one iteration per round, so every iteration expands the root",
+           "iterations": iters, "kernel_ms": ms, "us_per_iteration": 1e3 * ms / iters,
+           "expansions_per_s": exp / (ms / 1e3), "survival": ins / max(exp, 1),
+           "grid": st["grid"], "step_ms": [round(v, 3) for v in st["step_ms"]],
+           "roofline": {"bound": "alu", "kernel": "k_plan<QUAD>", "achieved": tf,
+                        "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": tf / FP32_VECTOR_PEAK_TFLOPS}}
+    pl.close()
+    return out
+
+
 def cpu_baseline(prob, seconds):
     """Time the FP64 reference (single thread) on the same query for ~`seconds`."""
     import oracle
@@ -320,6 +357,8 @@ def main():
     ap.add_argument("--no-other-systems", action="store_true")
     ap.add_argument("--other-systems-ms", type=float, default=100.0)
     ap.add_argument("--other-systems-seeds", type=int, default=3)
+    ap.add_argument("--no-saturating-rollout", action="store_true")
+    ap.add_argument("--saturating-iters", type=int, default=50)
     ap.add_argument("--refine-budget-ms", type=float, default=500.0)
     ap.add_argument("--refine-paths", type=int, default=256)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -443,6 +482,7 @@ def main():
         "batched": None,
         "refinement": None,
         "other_systems": None,
+        "saturating_rollout": None,
     }
     for p in plans:
         p.close()
@@ -457,6 +497,8 @@ def main():
     if not args.no_other_systems:
         out["other_systems"] = other_systems_leg(torch, pakr, W, args.other_systems_ms,
                                                  args.other_systems_seeds)
+    if not args.no_saturating_rollout:
+        out["saturating_rollout"] = saturating_rollout_leg(torch, pakr, W, args.saturating_iters)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W.config_c2(seed=0), args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 from paper_2607_03987_amd import pakr, workloads as W
-from tests.parity import rel_err
+from tests.parity import rel_err, step_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -103,3 +103,18 @@ def test_batched_form_at_bench_size_equals_single_query_plans():
                [(s["round"], s["iter"], s["node"], s["cost"]) for s in single.solutions()], q
         single.close()
     bp.close()
+
+
+@pytest.mark.parametrize("one_iter_rounds", [True, False])
+def test_step_parity_at_the_largest_batch(one_iter_rounds):
+    """B = 65536, the largest batch one launch takes, on the quadrotor: every
+    iteration replayed whole by the reference, from the root each time (the
+    shape of bench.py's saturating-rollout measurement) or on the tree the
+    first iteration grew."""
+    kw = dict(B=65536, A=16, n_cap=1 << 20)
+    if one_iter_rounds:
+        kw["max_iters_per_round"] = 1
+    prob = W.config_c4(**kw)
+    print(f"case c4 B 65536 A 16 one-iteration rounds {one_iter_rounds}", flush=True)
+    stats = step_parity(prob, 2, log=lambda m: print(m, flush=True))
+    assert sum(s["valid"] for s in stats) > 0
