@@ -599,7 +599,10 @@ __global__ __launch_bounds__(WAVE) void k_check_path(TrajArgs a) {
 #pragma unroll
       for (int c = 0; c < NP; ++c) pos[0][c] = x[c];
       const bool hit = any_obstacle_hit<NP, 1>(pos, s_obs, P.n_box, P.n_sph, lane, WAVE);
-      ok = ok & limits_ok<SYS>(s_val, x) & (__ballot(hit) == 0ull);
+      // every lane takes part in the ballot, whatever its own verdict so far
+      const bool clear = __ballot(hit) == 0ull;
+      const bool lim = limits_ok<SYS>(s_val, x);
+      ok = ok && lim && clear;
     }
     cost += P.cost_kind == PAKR_COST_PATH_LENGTH ? len : P.edge_duration;
   }

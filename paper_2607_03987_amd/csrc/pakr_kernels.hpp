@@ -221,7 +221,6 @@ struct Smem {
   float* tile;                 // [D][TILE] NN tile, 16-byte aligned
   float* targets;              // [D][NN_KC<QT>] the NN chunk's targets
   unsigned long long* keys;    // [NN_KC<QT>] their best keys over the node slices
-  unsigned long long* best;    // [NT] parent keys of a rollout chunk
   int* cnt;                    // [MAX_GR] survivors per rollout chunk
   int* off;                    // [MAX_GR + 1] their exclusive prefix
   int* wave;                   // [NT / WAVE]
@@ -246,7 +245,6 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
   float* const s_q = sm.targets;
   unsigned long long* const s_key = sm.keys;
   constexpr int KCM = NN_KC<QT>;
-  unsigned long long* const s_best = sm.best;
   int* const s_cnt = sm.cnt;
   int* const s_off = sm.off;
   int* const s_wave = sm.wave;
@@ -470,15 +468,8 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
     // ---------------- phase 2: controls, rollout, validity, prune ---------
     for (int rb = b; rb < GR; rb += G) {
       const int j0 = rb * CPB;
-      const int j1 = min(B, j0 + CPB);
-      const int k0 = j0 / A;
-      const int nql = (j1 - 1) / A - k0 + 1;
-      __syncthreads();  // the previous chunk's readers of s_best / s_goal are done
-      for (int i = tid; i < nql; i += NT) s_best[i] = ~0ull;
+      __syncthreads();  // the previous chunk's readers of s_goal are done
       if (tid == 0) s_goal = ~0ull;
-      __syncthreads();
-      for (int i = tid; i < nql; i += NT) s_best[i] = nnk[k0 + i];
-      __syncthreads();
       mark(2);
 
       // L consecutive lanes share candidate j: each integrates the edge and
@@ -496,7 +487,9 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
       if (active) {
         k = j / A;
         br = j - k * A;
-        parent = (int)(uint32_t)(s_best[k - k0] & 0xffffffffull);
+        // the lanes of a candidate and the A candidates of a target read the
+        // same key: one cache line serves a wave
+        parent = (int)(uint32_t)(nnk[k] & 0xffffffffull);
         sample_control<M>(P, (uint32_t)k, (uint32_t)br, (uint32_t)iter, (uint32_t)round, u);
 #pragma unroll
         for (int c = 0; c < D; ++c) x[c] = a.states[(size_t)c * NC + parent];
@@ -785,8 +778,7 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
 }
 
 __device__ __forceinline__ Smem make_smem(float* obs, float* tile, float* targets,
-                                          unsigned long long* keys, unsigned long long* best,
-                                          int* cnt, int* off, int* wave, float* val,
+                                          unsigned long long* keys, int* cnt, int* off, int* wave, float* val,
                                           unsigned long long* goal, int* fail, int* misc,
                                           Books* books) {
   Smem m;
@@ -794,7 +786,6 @@ __device__ __forceinline__ Smem make_smem(float* obs, float* tile, float* target
   m.tile = tile;
   m.targets = targets;
   m.keys = keys;
-  m.best = best;
   m.cnt = cnt;
   m.off = off;
   m.wave = wave;
@@ -813,7 +804,6 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
   __shared__ __align__(16) float s_tile[Sys<SYS>::D * TILE];
   __shared__ float s_targets[Sys<SYS>::D * NN_KC<QT>];
   __shared__ unsigned long long s_keys[NN_KC<QT>];
-  __shared__ unsigned long long s_best[NT];
   __shared__ int s_cnt[MAX_GR];
   __shared__ int s_off[MAX_GR + 1];
   __shared__ int s_wave[NT / WAVE];
@@ -822,7 +812,7 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
   __shared__ int s_fail;
   __shared__ int s_misc[2];
   __shared__ Books s_books;
-  const Smem sm = make_smem(s_obs, s_tile, s_targets, s_keys, s_best, s_cnt, s_off, s_wave, s_val,
+  const Smem sm = make_smem(s_obs, s_tile, s_targets, s_keys, s_cnt, s_off, s_wave, s_val,
                             &s_goal, &s_fail, s_misc, &s_books);
   // (above 6 state dimensions the plan keeps the plain scan: the node-slice
   // form costs the quadrotor's rollout code more than it saves)
@@ -844,7 +834,6 @@ __global__ __launch_bounds__(NT) void k_batch(const KArgs* __restrict__ qs,
   __shared__ __align__(16) float s_tile[PAKR_MAX_D * TILE];
   __shared__ float s_targets[PAKR_MAX_D * NN_KC<1>];
   __shared__ unsigned long long s_keys[NN_KC<1>];
-  __shared__ unsigned long long s_best[NT];
   __shared__ int s_cnt[MAX_GR];
   __shared__ int s_off[MAX_GR + 1];
   __shared__ int s_wave[NT / WAVE];
@@ -854,7 +843,7 @@ __global__ __launch_bounds__(NT) void k_batch(const KArgs* __restrict__ qs,
   __shared__ int s_misc[2];
   __shared__ int s_ticket;
   __shared__ Books s_books;
-  const Smem sm = make_smem(s_obs, s_tile, s_targets, s_keys, s_best, s_cnt, s_off, s_wave, s_val,
+  const Smem sm = make_smem(s_obs, s_tile, s_targets, s_keys, s_cnt, s_off, s_wave, s_val,
                             &s_goal, &s_fail, s_misc, &s_books);
   while (true) {
     __syncthreads();  // everyone has read the previous s_ticket
