@@ -88,7 +88,8 @@ enum pakr_error {
   PAKR_E_HIP = -5,                  /* a HIP runtime call failed                 */
   PAKR_E_NO_SOLUTION = -6,          /* no solution found yet                     */
   PAKR_E_BUFFER_TOO_SMALL = -7,     /* caller buffer cannot hold the result      */
-  PAKR_E_DEVICE = -8                /* device-side failure (grid barrier timeout) */
+  PAKR_E_DEVICE = -8                /* a grid barrier timed out on the device; the plan
+                                       or batch refuses every later launch          */
 };
 
 /* Status bits reported in pakr_stats.status (why the last call stopped). */
@@ -99,7 +100,9 @@ enum pakr_status_bits {
   PAKR_S_ITERS_DONE = 8,      /* the iteration budget of the call was used  */
   PAKR_S_TREE_FULL = 16,      /* some round ended with a full tree          */
   PAKR_S_ITER_CAP = 32,       /* some round hit max_iters_per_round         */
-  PAKR_S_DEVICE_ERROR = 64    /* a grid barrier timed out (see PAKR_E_DEVICE) */
+  PAKR_S_DEVICE_ERROR = 64    /* the call's guard time (its budget + 60 s of device
+                                 clock) ran out; a grid barrier that times out is
+                                 reported as PAKR_E_DEVICE instead             */
 };
 
 /* Dynamics and limits of one system.  Every field is required; the Python
@@ -304,16 +307,32 @@ int pakr_batch_replan(pakr_batch* batch, double budget_ms, int max_rounds, long 
 
 /* Capture (work-queue reset + batch launch with these limits) into a
  * hipGraph, replayed by pakr_batch_graph_launch on the batch's stream.
- * Captured on an internal stream; replaces any earlier capture.  Syncs. */
+ * Captured on an internal stream; replaces any earlier capture.  The graph
+ * keeps its own device copy of the limits, so later pakr_batch_replan or
+ * pakr_batch_expand calls do not change what a replay runs.  Syncs. */
 int pakr_batch_graph_capture(pakr_batch* batch, double budget_ms, int max_rounds,
                              long long max_iters);
 int pakr_batch_graph_launch(pakr_batch* batch);
 
-/* Per-query results (sync); same meaning as the single-query calls. */
+/* One launch that runs exactly n_iters inner iterations of Alg. 1 for every
+ * query (rounds end and restart as for pakr_expand), recording query q's
+ * iterations into d_traces[q] (device, >= pakr_batch_trace_bytes(batch, q,
+ * n_iters), record layout as for pakr_expand).  d_traces and trace_bytes
+ * are host arrays of n entries; d_traces or any entry may be NULL (no trace
+ * for that query).  Async. */
+size_t pakr_batch_trace_bytes(const pakr_batch* batch, int q, int n_iters);
+int pakr_batch_expand(pakr_batch* batch, int n_iters, void* const* d_traces,
+                      const size_t* trace_bytes);
+
+/* Per-query results (sync); same meaning as the single-query calls.  After a
+ * grid barrier timed out in any query they return PAKR_E_DEVICE, and the
+ * batch refuses every later launch. */
 int pakr_batch_status(pakr_batch* batch, int q, pakr_stats* out);
 int pakr_batch_solutions(pakr_batch* batch, int q, pakr_solution* out, int cap, int* n_total);
 int pakr_batch_extract_path(pakr_batch* batch, int q, float* states, float* actions,
                             int cap_edges, int* n_edges, double* cost);
+int pakr_batch_copy_tree(pakr_batch* batch, int q, float* states, float* actions, int* parents,
+                         float* costs, int n_max, int* n);
 
 /* Workgroups of the batch launch (queries run concurrently). */
 int pakr_batch_grid(const pakr_batch* batch);
@@ -410,6 +429,13 @@ int pakr_check_path(pakr_refiner* r, int n, int M, const float* d_x0, const floa
 
 const char* pakr_refiner_last_error(const pakr_refiner* r);
 void pakr_refiner_destroy(pakr_refiner* r);
+
+/* How long a workgroup of any later launch waits at a grid barrier before
+ * the call fails (every workgroup then leaves the kernel, and the next
+ * status or read-back call returns PAKR_E_DEVICE).  Process-wide; ms <= 0
+ * restores the default of 2000 ms.  A tiny value forces that failure path
+ * from the host (failure-handling tests).  PAKR_E_INVALID_ARG for NaN. */
+int pakr_set_barrier_timeout(double ms);
 
 /* Static name of an error code. */
 const char* pakr_error_string(int code);

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -19,7 +20,14 @@ namespace {
 constexpr int AUTO_GRID_MAX = 1024;      // workspace sizing bound for grid = 0
 constexpr int DEFAULT_PATH_EDGES = 4096;
 
-thread_local std::string g_init_error;
+// Message of the last failed init call on this thread.  A plain character
+// array: a thread_local with a destructor would register an exit-time
+// handler in this library, which runs after the HIP runtime may be gone.
+thread_local char g_init_error[512];
+
+void set_init_error(const std::string& msg) {
+  std::snprintf(g_init_error, sizeof g_init_error, "%s", msg.c_str());
+}
 
 struct Layout {
   size_t hdr, bar, sols, pstates, pactions, states, actions, parents, costs, obs, nn_keys, stg,
@@ -424,6 +432,11 @@ KArgs make_args(const DevProblem& Q, char* base, const Layout& L) {
   return a;
 }
 
+// How long a workgroup waits at a grid barrier before the call fails with
+// PAKR_E_DEVICE (pakr_set_barrier_timeout; read at every launch).
+constexpr double DEFAULT_BARRIER_TIMEOUT_MS = 2000.0;
+std::atomic<double> g_barrier_timeout_ms{DEFAULT_BARRIER_TIMEOUT_MS};
+
 void set_limits(KArgs& a, long long max_iters, long long max_rounds, double budget_ms,
                 double ticks_per_ms) {
   a.max_iters = max_iters;
@@ -431,7 +444,14 @@ void set_limits(KArgs& a, long long max_iters, long long max_rounds, double budg
   a.budget_ticks = budget_ms > 0 ? (long long)(budget_ms * ticks_per_ms) : 0;
   const double guard_ms = (budget_ms > 0 ? budget_ms : 0.0) + 60000.0;
   a.guard_ticks = (long long)(guard_ms * ticks_per_ms);
-  a.barrier_timeout_ticks = (long long)(2000.0 * ticks_per_ms);
+  a.barrier_timeout_ticks =
+      std::max(1ll, (long long)(g_barrier_timeout_ms.load() * ticks_per_ms));
+}
+
+// Int32 words of one trace record of a query (layout in pakr.h).
+size_t trace_words_of(const DevProblem& P) {
+  const size_t K = P.K, B = P.B, d = P.d, m = P.m;
+  return TRACE_HDR_WORDS + K * d + K + B * m + B * d + 3 * B;
 }
 
 // Copy the obstacles and enqueue the root write of one query.
@@ -543,6 +563,32 @@ hipError_t read_path(const KArgs& a, int ne, float* states, float* actions) {
   return hipSuccess;
 }
 
+// The first n nodes of a query's tree, node-major (any output may be null).
+hipError_t read_tree(const KArgs& a, int n, float* states, float* actions, int* parents,
+                     float* costs) {
+  const int d = a.P.d, m = a.P.m;
+  const size_t N = (size_t)a.P.n_cap;
+  hipError_t e = hipSuccess;
+  if (n > 0 && (states || actions)) {
+    std::vector<float> tmp((size_t)n);
+    for (int c = 0; c < d && states && e == hipSuccess; ++c) {
+      e = hipMemcpy(tmp.data(), a.states + (size_t)c * N, sizeof(float) * n,
+                    hipMemcpyDeviceToHost);
+      for (int i = 0; i < n; ++i) states[(size_t)i * d + c] = tmp[i];
+    }
+    for (int c = 0; c < m && actions && e == hipSuccess; ++c) {
+      e = hipMemcpy(tmp.data(), a.actions + (size_t)c * N, sizeof(float) * n,
+                    hipMemcpyDeviceToHost);
+      for (int i = 0; i < n; ++i) actions[(size_t)i * m + c] = tmp[i];
+    }
+  }
+  if (e == hipSuccess && n > 0 && parents)
+    e = hipMemcpy(parents, a.parents, sizeof(int) * n, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && n > 0 && costs)
+    e = hipMemcpy(costs, a.costs, sizeof(float) * n, hipMemcpyDeviceToHost);
+  return e;
+}
+
 }  // namespace
 
 struct pakr_plan {
@@ -568,7 +614,8 @@ struct pakr_batch {
   bool own_ws = false;
   std::vector<KArgs> args;
   std::vector<int> team;   // workgroups per query
-  KArgs* d_args = nullptr;
+  KArgs* d_args = nullptr;        // argument table of direct launches (replan, expand)
+  KArgs* d_args_graph = nullptr;  // the captured graph's own table (its limits)
   int* d_tickets = nullptr;
   int n_tickets = 0;
   int* d_queue = nullptr;
@@ -584,7 +631,7 @@ namespace {
 
 int fail(pakr_plan* pl, int code, const std::string& msg) {
   if (pl) pl->err = msg;
-  else g_init_error = msg;
+  else set_init_error(msg);
   return code;
 }
 
@@ -594,7 +641,7 @@ int hip_fail(pakr_plan* pl, hipError_t e, const char* what) {
 
 int bfail(pakr_batch* bt, int code, const std::string& msg) {
   if (bt) bt->err = msg;
-  else g_init_error = msg;
+  else set_init_error(msg);
   return code;
 }
 
@@ -730,9 +777,7 @@ void pakr_plan_destroy(pakr_plan* pl) {
 
 size_t pakr_trace_bytes(const pakr_plan* pl, int n_iters) {
   if (!pl || n_iters < 0) return 0;
-  const size_t K = pl->args.P.K, B = pl->args.P.B, d = pl->args.P.d, m = pl->args.P.m;
-  const size_t words = TRACE_HDR_WORDS + K * d + K + B * m + B * d + 3 * B;
-  return words * 4 * (size_t)n_iters;
+  return trace_words_of(pl->args.P) * 4 * (size_t)n_iters;
 }
 
 namespace {
@@ -829,33 +874,19 @@ int pakr_copy_tree(pakr_plan* pl, float* states, float* actions, int* parents, f
   int rc = sync_header(pl, &h);
   if (rc != PAKR_OK) return rc;
   *n_out = h.n;
-  const int n = std::min(h.n, n_max);
-  const int d = pl->args.P.d, m = pl->args.P.m;
-  const size_t N = (size_t)pl->args.P.n_cap;
-  hipError_t e = hipSuccess;
-  if (n > 0 && (states || actions)) {
-    std::vector<float> tmp((size_t)n);
-    for (int c = 0; c < d && states && e == hipSuccess; ++c) {
-      e = hipMemcpy(tmp.data(), pl->args.states + (size_t)c * N, sizeof(float) * n,
-                    hipMemcpyDeviceToHost);
-      for (int i = 0; i < n; ++i) states[(size_t)i * d + c] = tmp[i];
-    }
-    for (int c = 0; c < m && actions && e == hipSuccess; ++c) {
-      e = hipMemcpy(tmp.data(), pl->args.actions + (size_t)c * N, sizeof(float) * n,
-                    hipMemcpyDeviceToHost);
-      for (int i = 0; i < n; ++i) actions[(size_t)i * m + c] = tmp[i];
-    }
-  }
-  if (e == hipSuccess && n > 0 && parents)
-    e = hipMemcpy(parents, pl->args.parents, sizeof(int) * n, hipMemcpyDeviceToHost);
-  if (e == hipSuccess && n > 0 && costs)
-    e = hipMemcpy(costs, pl->args.costs, sizeof(float) * n, hipMemcpyDeviceToHost);
+  hipError_t e = read_tree(pl->args, std::min(h.n, n_max), states, actions, parents, costs);
   if (e != hipSuccess) return hip_fail(pl, e, "read tree");
   return PAKR_OK;
 }
 
 const char* pakr_last_error(const pakr_plan* pl) {
-  return pl ? pl->err.c_str() : g_init_error.c_str();
+  return pl ? pl->err.c_str() : g_init_error;
+}
+
+int pakr_set_barrier_timeout(double ms) {
+  if (std::isnan(ms)) return PAKR_E_INVALID_ARG;
+  g_barrier_timeout_ms.store(ms > 0 ? ms : DEFAULT_BARRIER_TIMEOUT_MS);
+  return PAKR_OK;
 }
 
 const char* pakr_error_string(int code) {
@@ -898,11 +929,13 @@ int batch_lanes(const pakr_params& p) { return p.lanes_per_candidate > 0 ? p.lan
 // Workgroups that share one query of a batch ("team"): at most TEAM_MAX.
 constexpr int TEAM_MAX = 16;
 
-// Offsets of the batch workspace: queue word, argument table, then one
-// single-workgroup query layout after another.
-// Batch workspace: queue word, the argument table, the ticket table, then each
-// query's regions, sized for a team of up to TEAM_MAX workgroups.
-size_t batch_tickets_offset(int n) { return 256 + align_up(sizeof(KArgs) * (size_t)n); }
+// Batch workspace: queue word, the argument table of direct launches, the
+// captured graph's argument table, the ticket table, then each query's
+// regions, sized for a team of up to TEAM_MAX workgroups.
+size_t batch_args_offset(int n, int which) {
+  return 256 + (size_t)which * align_up(sizeof(KArgs) * (size_t)n);
+}
+size_t batch_tickets_offset(int n) { return batch_args_offset(n, 2); }
 
 size_t batch_layout(int n, const pakr_system* sys, const pakr_scene* sc, const pakr_params* prm,
                     std::vector<size_t>* bases, std::vector<Layout>* layouts) {
@@ -996,7 +1029,8 @@ int pakr_batch_init(int n, const pakr_system* sys, const pakr_scene* scenes,
   }
   char* base = static_cast<char*>(bt->ws);
   bt->d_queue = reinterpret_cast<int*>(base);
-  bt->d_args = reinterpret_cast<KArgs*>(base + 256);
+  bt->d_args = reinterpret_cast<KArgs*>(base + batch_args_offset(n, 0));
+  bt->d_args_graph = reinterpret_cast<KArgs*>(base + batch_args_offset(n, 1));
   bt->d_tickets = reinterpret_cast<int*>(base + batch_tickets_offset(n));
   // Team sizes: params.grid if set, else the query's share of the estimated
   // work of the whole batch in workgroups (at least 1, at most TEAM_MAX).
@@ -1054,20 +1088,20 @@ int pakr_batch_init(int n, const pakr_system* sys, const pakr_scene* scenes,
 
 namespace {
 
-// Upload the argument table with these limits and enqueue reset + launch on `s`.
-int batch_enqueue(pakr_batch* bt, double budget_ms, int max_rounds, long long max_iters,
-                  hipStream_t s, bool upload) {
-  if (upload) {
-    for (auto& a : bt->args) set_limits(a, max_iters, max_rounds, budget_ms, bt->ticks_per_ms);
-    hipError_t e = hipMemcpyAsync(bt->d_args, bt->args.data(), sizeof(KArgs) * bt->args.size(),
-                                  hipMemcpyHostToDevice, bt->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(bt->stream);  // pageable source
-    if (e != hipSuccess) return bhip_fail(bt, e, "upload batch arguments");
-  }
+// Upload `table` (one record per query) to `d_table`; syncs the batch stream.
+int batch_upload(pakr_batch* bt, const std::vector<KArgs>& table, KArgs* d_table) {
+  hipError_t e = hipMemcpyAsync(d_table, table.data(), sizeof(KArgs) * table.size(),
+                                hipMemcpyHostToDevice, bt->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(bt->stream);  // pageable source
+  if (e != hipSuccess) return bhip_fail(bt, e, "upload batch arguments");
+  return PAKR_OK;
+}
+
+// Enqueue the queue reset and the persistent launch reading `d_table` on `s`.
+int batch_enqueue(pakr_batch* bt, const KArgs* d_table, hipStream_t s) {
   hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, bt->d_queue);
-  hipLaunchKernelGGL(k_batch, dim3(bt->G), dim3(NT), bt->shmem, s,
-                     static_cast<const KArgs*>(bt->d_args), static_cast<const int*>(bt->d_tickets),
-                     bt->n_tickets, bt->d_queue);
+  hipLaunchKernelGGL(k_batch, dim3(bt->G), dim3(NT), bt->shmem, s, d_table,
+                     static_cast<const int*>(bt->d_tickets), bt->n_tickets, bt->d_queue);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return bhip_fail(bt, e, "batch launch");
   return PAKR_OK;
@@ -1080,19 +1114,77 @@ int batch_limits_ok(pakr_batch* bt, double budget_ms, int max_rounds, long long 
   return PAKR_OK;
 }
 
+int batch_usable(pakr_batch* bt) {
+  if (bt->broken) return bfail(bt, PAKR_E_DEVICE, "batch is unusable after a device error");
+  return PAKR_OK;
+}
+
+// The argument table with these limits (and no trace).
+std::vector<KArgs> batch_table(const pakr_batch* bt, double budget_ms, int max_rounds,
+                               long long max_iters) {
+  std::vector<KArgs> t = bt->args;
+  for (auto& a : t) set_limits(a, max_iters, max_rounds, budget_ms, bt->ticks_per_ms);
+  return t;
+}
+
+// Query q's header (syncs the batch stream); a device error in any query
+// (a grid barrier that timed out) leaves the batch's barrier words in an
+// unknown state, so the batch refuses every later launch.
+int batch_header(pakr_batch* bt, int q, DevHeader* h) {
+  hipError_t e = read_header(bt->args[q], bt->stream, h);
+  if (e != hipSuccess) return bhip_fail(bt, e, "read header");
+  if (h->err != 0) {
+    bt->broken = true;
+    return bfail(bt, PAKR_E_DEVICE,
+                 "query " + std::to_string(q) + ": grid barrier timed out on the device");
+  }
+  return PAKR_OK;
+}
+
 }  // namespace
 
 int pakr_batch_replan(pakr_batch* bt, double budget_ms, int max_rounds, long long max_iters) {
   if (!bt) return PAKR_E_INVALID_ARG;
-  int rc = batch_limits_ok(bt, budget_ms, max_rounds, max_iters);
+  int rc = batch_usable(bt);
+  if (rc == PAKR_OK) rc = batch_limits_ok(bt, budget_ms, max_rounds, max_iters);
+  if (rc == PAKR_OK) rc = batch_upload(bt, batch_table(bt, budget_ms, max_rounds, max_iters),
+                                       bt->d_args);
+  if (rc == PAKR_OK) rc = batch_enqueue(bt, bt->d_args, bt->stream);
+  return rc;
+}
+
+size_t pakr_batch_trace_bytes(const pakr_batch* bt, int q, int n_iters) {
+  if (!bt || q < 0 || q >= bt->nq || n_iters < 0) return 0;
+  return trace_words_of(bt->args[q].P) * 4 * (size_t)n_iters;
+}
+
+int pakr_batch_expand(pakr_batch* bt, int n_iters, void* const* d_traces,
+                      const size_t* trace_bytes) {
+  if (!bt) return PAKR_E_INVALID_ARG;
+  int rc = batch_usable(bt);
   if (rc != PAKR_OK) return rc;
-  return batch_enqueue(bt, budget_ms, max_rounds, max_iters, bt->stream, true);
+  if (n_iters < 0) return bfail(bt, PAKR_E_INVALID_ARG, "n_iters must be >= 0");
+  if (n_iters == 0) return PAKR_OK;
+  std::vector<KArgs> t = batch_table(bt, 0.0, 0, n_iters);
+  for (int q = 0; q < bt->nq && d_traces; ++q) {
+    if (!d_traces[q]) continue;
+    if (!trace_bytes || trace_bytes[q] < pakr_batch_trace_bytes(bt, q, n_iters))
+      return bfail(bt, PAKR_E_BUFFER_TOO_SMALL,
+                   "query " + std::to_string(q) + ": trace buffer too small");
+    t[q].trace = static_cast<int*>(d_traces[q]);
+    t[q].trace_words = (long long)trace_words_of(t[q].P);
+    t[q].trace_iters = n_iters;
+  }
+  rc = batch_upload(bt, t, bt->d_args);
+  if (rc == PAKR_OK) rc = batch_enqueue(bt, bt->d_args, bt->stream);
+  return rc;
 }
 
 int pakr_batch_graph_capture(pakr_batch* bt, double budget_ms, int max_rounds,
                              long long max_iters) {
   if (!bt) return PAKR_E_INVALID_ARG;
-  int rc = batch_limits_ok(bt, budget_ms, max_rounds, max_iters);
+  int rc = batch_usable(bt);
+  if (rc == PAKR_OK) rc = batch_limits_ok(bt, budget_ms, max_rounds, max_iters);
   if (rc != PAKR_OK) return rc;
   if (bt->gexec) {
     (void)hipGraphExecDestroy(bt->gexec);
@@ -1105,18 +1197,19 @@ int pakr_batch_graph_capture(pakr_batch* bt, double budget_ms, int max_rounds,
   hipError_t e = hipSuccess;
   if (!bt->cap_stream) e = hipStreamCreateWithFlags(&bt->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) return bhip_fail(bt, e, "create capture stream");
-  // the argument table is uploaded once, outside the graph
-  for (auto& a : bt->args) set_limits(a, max_iters, max_rounds, budget_ms, bt->ticks_per_ms);
-  e = hipMemcpyAsync(bt->d_args, bt->args.data(), sizeof(KArgs) * bt->args.size(),
-                     hipMemcpyHostToDevice, bt->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(bt->stream);
-  if (e != hipSuccess) return bhip_fail(bt, e, "upload batch arguments");
+  // the graph's limits live in its own table, uploaded once outside the
+  // graph, so direct launches (which rewrite the other table) leave them alone
+  rc = batch_upload(bt, batch_table(bt, budget_ms, max_rounds, max_iters), bt->d_args_graph);
+  if (rc != PAKR_OK) return rc;
   e = hipStreamBeginCapture(bt->cap_stream, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return bhip_fail(bt, e, "begin capture");
-  rc = batch_enqueue(bt, budget_ms, max_rounds, max_iters, bt->cap_stream, false);
+  rc = batch_enqueue(bt, bt->d_args_graph, bt->cap_stream);
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(bt->cap_stream, &g);
-  if (rc != PAKR_OK) return rc;
+  if (rc != PAKR_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
   if (e != hipSuccess) return bhip_fail(bt, e, "end capture");
   bt->graph = g;
   e = hipGraphInstantiate(&bt->gexec, bt->graph, nullptr, nullptr, 0);
@@ -1126,6 +1219,8 @@ int pakr_batch_graph_capture(pakr_batch* bt, double budget_ms, int max_rounds,
 
 int pakr_batch_graph_launch(pakr_batch* bt) {
   if (!bt) return PAKR_E_INVALID_ARG;
+  int rc = batch_usable(bt);
+  if (rc != PAKR_OK) return rc;
   if (!bt->gexec) return bfail(bt, PAKR_E_INVALID_ARG, "no captured graph");
   hipError_t e = hipGraphLaunch(bt->gexec, bt->stream);
   if (e != hipSuccess) return bhip_fail(bt, e, "graph launch");
@@ -1135,8 +1230,8 @@ int pakr_batch_graph_launch(pakr_batch* bt) {
 int pakr_batch_status(pakr_batch* bt, int q, pakr_stats* out) {
   if (!bt || !out || q < 0 || q >= bt->nq) return PAKR_E_INVALID_ARG;
   DevHeader h;
-  hipError_t e = read_header(bt->args[q], bt->stream, &h);
-  if (e != hipSuccess) return bhip_fail(bt, e, "read header");
+  int rc = batch_header(bt, q, &h);
+  if (rc != PAKR_OK) return rc;
   fill_stats(h, bt->ticks_per_ms, bt->G, out);
   return PAKR_OK;
 }
@@ -1145,11 +1240,11 @@ int pakr_batch_solutions(pakr_batch* bt, int q, pakr_solution* out, int cap, int
   if (!bt || !n_total || q < 0 || q >= bt->nq || cap < 0 || (cap > 0 && !out))
     return PAKR_E_INVALID_ARG;
   DevHeader h;
-  hipError_t e = read_header(bt->args[q], bt->stream, &h);
-  if (e != hipSuccess) return bhip_fail(bt, e, "read header");
+  int rc = batch_header(bt, q, &h);
+  if (rc != PAKR_OK) return rc;
   *n_total = h.n_solutions;
-  e = read_solutions(bt->args[q], bt->ticks_per_ms,
-                     std::min(std::min(cap, h.n_solutions), MAX_SOLUTIONS), out);
+  hipError_t e = read_solutions(bt->args[q], bt->ticks_per_ms,
+                                std::min(std::min(cap, h.n_solutions), MAX_SOLUTIONS), out);
   if (e != hipSuccess) return bhip_fail(bt, e, "read solutions");
   return PAKR_OK;
 }
@@ -1158,8 +1253,8 @@ int pakr_batch_extract_path(pakr_batch* bt, int q, float* states, float* actions
                             int* n_edges, double* cost) {
   if (!bt || !n_edges || q < 0 || q >= bt->nq) return PAKR_E_INVALID_ARG;
   DevHeader h;
-  hipError_t e = read_header(bt->args[q], bt->stream, &h);
-  if (e != hipSuccess) return bhip_fail(bt, e, "read header");
+  int rc = batch_header(bt, q, &h);
+  if (rc != PAKR_OK) return rc;
   if (h.best_edges < 0) {
     *n_edges = 0;
     return bfail(bt, PAKR_E_NO_SOLUTION, "no solution yet");
@@ -1169,8 +1264,20 @@ int pakr_batch_extract_path(pakr_batch* bt, int q, float* states, float* actions
   if (h.path_truncated) return bfail(bt, PAKR_E_BUFFER_TOO_SMALL, "path longer than max_path_edges");
   if (h.best_edges > cap_edges) return bfail(bt, PAKR_E_BUFFER_TOO_SMALL, "cap_edges too small");
   if (!states || !actions) return bfail(bt, PAKR_E_INVALID_ARG, "null output arrays");
-  e = read_path(bt->args[q], h.best_edges, states, actions);
+  hipError_t e = read_path(bt->args[q], h.best_edges, states, actions);
   if (e != hipSuccess) return bhip_fail(bt, e, "read path");
+  return PAKR_OK;
+}
+
+int pakr_batch_copy_tree(pakr_batch* bt, int q, float* states, float* actions, int* parents,
+                         float* costs, int n_max, int* n_out) {
+  if (!bt || !n_out || n_max < 0 || q < 0 || q >= bt->nq) return PAKR_E_INVALID_ARG;
+  DevHeader h;
+  int rc = batch_header(bt, q, &h);
+  if (rc != PAKR_OK) return rc;
+  *n_out = h.n;
+  hipError_t e = read_tree(bt->args[q], std::min(h.n, n_max), states, actions, parents, costs);
+  if (e != hipSuccess) return bhip_fail(bt, e, "read tree");
   return PAKR_OK;
 }
 
@@ -1181,7 +1288,7 @@ int pakr_batch_team(const pakr_batch* bt, int q) {
 }
 
 const char* pakr_batch_last_error(const pakr_batch* bt) {
-  return bt ? bt->err.c_str() : g_init_error.c_str();
+  return bt ? bt->err.c_str() : g_init_error;
 }
 
 void pakr_batch_destroy(pakr_batch* bt) {
@@ -1212,7 +1319,7 @@ namespace {
 
 int rfail(pakr_refiner* r, int code, const std::string& msg) {
   if (r) r->err = msg;
-  else g_init_error = msg;
+  else set_init_error(msg);
   return code;
 }
 
@@ -1328,10 +1435,10 @@ int launch_accept(pakr_refiner* r, int n, int M, float* U, const float* Ut, floa
   a.J_trial = Jt;
   a.lr_traj = lr_traj;
   a.per_traj = M * r->P.m;
-  a.n = n * a.per_traj;
+  a.n_traj = n;
   void* args[] = {&a};
-  hipError_t e = hipLaunchKernel(reinterpret_cast<const void*>(&k_accept),
-                                 dim3((a.n + 255) / 256), dim3(256), args, 0, r->stream);
+  hipError_t e = hipLaunchKernel(reinterpret_cast<const void*>(&k_accept), dim3(n), dim3(WAVE),
+                                 args, 0, r->stream);
   if (e != hipSuccess) return rfail(r, PAKR_E_HIP, std::string("launch: ") + hipGetErrorString(e));
   return PAKR_OK;
 }
@@ -1498,20 +1605,26 @@ size_t pakr_refine_workspace_size(const pakr_refiner* r, int n, int M) {
   return refine_layout(r, n, M).total;
 }
 
-int pakr_refine_paths(pakr_refiner* r, int n, int M, const float* d_x0, float* d_U, int steps,
-                      float lr, void* d_ws, size_t ws_bytes, float* d_J_before, float* d_J_after) {
-  if (!r) return PAKR_E_INVALID_ARG;
+}  // extern "C"
+
+namespace {
+
+// Argument checks shared by the two refinement-loop entry points.
+int refine_args_ok(pakr_refiner* r, int n, int M, const float* d_x0, float* d_U, int steps,
+                   float lr) {
   if (!traj_sizes_ok(r, n, M) || (size_t)n * M * r->P.m > (size_t)INT32_MAX)
     return rfail(r, PAKR_E_INVALID_ARG, "bad trajectory count or M");
-  if (!d_x0 || !d_U || !d_ws) return rfail(r, PAKR_E_INVALID_ARG, "null device array");
+  if (!d_x0 || !d_U) return rfail(r, PAKR_E_INVALID_ARG, "null device array");
   if (steps < 0) return rfail(r, PAKR_E_INVALID_ARG, "steps must be >= 0");
   if (!(lr > 0.0f) || !std::isfinite(lr)) return rfail(r, PAKR_E_INVALID_ARG, "lr must be > 0");
-  const RefineLayout L = refine_layout(r, n, M);
-  if (ws_bytes < L.total)
-    return rfail(r, PAKR_E_WORKSPACE_TOO_SMALL, "workspace smaller than required");
-  if ((reinterpret_cast<uintptr_t>(d_ws) & 255) != 0)
-    return rfail(r, PAKR_E_INVALID_ARG, "workspace must be 256-byte aligned");
-  char* base = static_cast<char*>(d_ws);
+  return PAKR_OK;
+}
+
+// The refinement loop with its work buffers (layout L) at `base`: every
+// buffer that must start at a known value is filled by a kernel first.
+int refine_paths_at(pakr_refiner* r, int n, int M, const float* d_x0, float* d_U, int steps,
+                    float lr, char* base, const RefineLayout& L, float* d_J_before,
+                    float* d_J_after) {
   float* ckpt = reinterpret_cast<float*>(base + L.ckpt);
   float* m1 = reinterpret_cast<float*>(base + L.m1);
   float* m2 = reinterpret_cast<float*>(base + L.m2);
@@ -1561,6 +1674,25 @@ int pakr_refine_paths(pakr_refiner* r, int n, int M, const float* d_x0, float* d
   return rc;
 }
 
+}  // namespace
+
+extern "C" {
+
+int pakr_refine_paths(pakr_refiner* r, int n, int M, const float* d_x0, float* d_U, int steps,
+                      float lr, void* d_ws, size_t ws_bytes, float* d_J_before, float* d_J_after) {
+  if (!r) return PAKR_E_INVALID_ARG;
+  int rc = refine_args_ok(r, n, M, d_x0, d_U, steps, lr);
+  if (rc != PAKR_OK) return rc;
+  if (!d_ws) return rfail(r, PAKR_E_INVALID_ARG, "null device array");
+  const RefineLayout L = refine_layout(r, n, M);
+  if (ws_bytes < L.total)
+    return rfail(r, PAKR_E_WORKSPACE_TOO_SMALL, "workspace smaller than required");
+  if ((reinterpret_cast<uintptr_t>(d_ws) & 255) != 0)
+    return rfail(r, PAKR_E_INVALID_ARG, "workspace must be 256-byte aligned");
+  return refine_paths_at(r, n, M, d_x0, d_U, steps, lr, static_cast<char*>(d_ws), L, d_J_before,
+                         d_J_after);
+}
+
 int pakr_check_path(pakr_refiner* r, int n, int M, const float* d_x0, const float* d_U,
                     int* d_ok, float* d_cost) {
   if (!r) return PAKR_E_INVALID_ARG;
@@ -1575,7 +1707,7 @@ int pakr_check_path(pakr_refiner* r, int n, int M, const float* d_x0, const floa
 }
 
 const char* pakr_refiner_last_error(const pakr_refiner* r) {
-  return r ? r->err.c_str() : g_init_error.c_str();
+  return r ? r->err.c_str() : g_init_error;
 }
 
 void pakr_refiner_destroy(pakr_refiner* r) {

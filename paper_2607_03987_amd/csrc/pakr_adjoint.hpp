@@ -648,25 +648,30 @@ __global__ __launch_bounds__(256) void k_adam_project(AdamArgs a) {
 // Safeguard of the refinement loop: a trial that lowers J replaces the
 // current controls and lets its trajectory's step grow (up to the base
 // step); a trial that does not is dropped and the step is halved.
-// One lane per control value; the first value of a trajectory updates its
-// step factor and J.
+// One 64-lane workgroup per trajectory: every lane reads J and J_trial, all
+// of them copy the trial controls if it is taken, and only after a workgroup
+// barrier does lane 0 overwrite J (so no lane can see the updated J and take
+// a different decision).
 struct AcceptArgs {
   float* U;
   const float* U_trial;
   float* J;                       // J of U; becomes min(J, J_trial)
   const float* J_trial;
   float* lr_traj;
-  int n, per_traj;
+  int n_traj, per_traj;
 };
 
-__global__ __launch_bounds__(256) void k_accept(AcceptArgs a) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
-  const int p = i / a.per_traj;
+__global__ __launch_bounds__(WAVE) void k_accept(AcceptArgs a) {
+  const int p = blockIdx.x;
+  if (p >= a.n_traj) return;
   const float J = a.J[p], Jt = a.J_trial[p];
   const bool take = Jt < J;  // NaN trials are never taken
-  if (take) a.U[i] = a.U_trial[i];
-  if (i == p * a.per_traj) {
+  if (take) {
+    const size_t base = (size_t)p * a.per_traj;
+    for (int i = threadIdx.x; i < a.per_traj; i += blockDim.x) a.U[base + i] = a.U_trial[base + i];
+  }
+  __syncthreads();  // every lane has read J before it changes
+  if (threadIdx.x == 0) {
     a.lr_traj[p] = take ? fminf(a.lr_traj[p] * 1.25f, 1.0f) : a.lr_traj[p] * 0.5f;
     if (take) a.J[p] = Jt;
   }

@@ -39,7 +39,8 @@ EXPORTED = ["pakr_workspace_size", "pakr_plan_init", "pakr_plan_destroy", "pakr_
             "pakr_batch_workspace_size", "pakr_batch_init", "pakr_batch_replan",
             "pakr_batch_graph_capture", "pakr_batch_graph_launch", "pakr_batch_status",
             "pakr_batch_solutions", "pakr_batch_extract_path", "pakr_batch_grid",
-            "pakr_batch_team",
+            "pakr_batch_team", "pakr_batch_trace_bytes", "pakr_batch_expand",
+            "pakr_batch_copy_tree", "pakr_set_barrier_timeout",
             "pakr_batch_last_error", "pakr_batch_destroy",
             "pakr_refiner_init", "pakr_refiner_set_params", "pakr_rollout_ckpt_bytes",
             "pakr_rollout_fwd", "pakr_rollout_bwd", "pakr_refine_step", "pakr_check_path",
@@ -171,6 +172,16 @@ def load():
         L.pakr_batch_grid.restype = C.c_int
         L.pakr_batch_team.argtypes = [vp, C.c_int]
         L.pakr_batch_team.restype = C.c_int
+        L.pakr_batch_trace_bytes.argtypes = [vp, C.c_int, C.c_int]
+        L.pakr_batch_trace_bytes.restype = sz
+        L.pakr_batch_expand.argtypes = [vp, C.c_int, C.POINTER(vp), C.POINTER(sz)]
+        L.pakr_batch_expand.restype = C.c_int
+        L.pakr_batch_copy_tree.argtypes = [vp, C.c_int, C.POINTER(C.c_float),
+                                           C.POINTER(C.c_float), C.POINTER(C.c_int),
+                                           C.POINTER(C.c_float), C.c_int, C.POINTER(C.c_int)]
+        L.pakr_batch_copy_tree.restype = C.c_int
+        L.pakr_set_barrier_timeout.argtypes = [C.c_double]
+        L.pakr_set_barrier_timeout.restype = C.c_int
         L.pakr_batch_last_error.argtypes = [vp]
         L.pakr_batch_last_error.restype = C.c_char_p
         L.pakr_batch_destroy.argtypes = [vp]
@@ -366,43 +377,57 @@ class Plan:
         return states, actions[:n], cost.value
 
     def copy_tree(self):
-        n = C.c_int(0)
-        _check(load().pakr_copy_tree(self.h, None, None, None, None, 0, C.byref(n)), self.h)
-        nn = n.value
-        states = np.zeros((nn, self.d), np.float32)
-        actions = np.zeros((nn, self.m), np.float32)
-        parents = np.zeros(nn, np.int32)
-        costs = np.zeros(nn, np.float32)
-        _check(load().pakr_copy_tree(self.h, _fp(states), _fp(actions),
-                                     parents.ctypes.data_as(C.POINTER(C.c_int)), _fp(costs), nn,
-                                     C.byref(n)), self.h)
-        return states, actions, parents, costs
+        return _copy_tree(lambda *a: _check(load().pakr_copy_tree(self.h, *a), self.h),
+                          self.d, self.m)
 
     # --- trace decoding ----------------------------------------------------
     def decode_trace(self, words: np.ndarray, n_iters: int) -> list:
-        K, B, d, m = self.K, self.B, self.d, self.m
-        per = TRACE_HDR_WORDS + K * d + K + B * m + B * d + 3 * B
-        out = []
-        for i in range(n_iters):
-            w = words[i * per:(i + 1) * per]
-            h = w[:TRACE_HDR_WORDS]
-            o = TRACE_HDR_WORDS
-            f32 = lambda a: a.view(np.float32)
-            targets = f32(w[o:o + K * d]).reshape(K, d); o += K * d
-            parents = w[o:o + K].copy(); o += K
-            controls = f32(w[o:o + B * m]).reshape(B, m); o += B * m
-            xnew = f32(w[o:o + B * d]).reshape(B, d); o += B * d
-            cnew = f32(w[o:o + B]).copy(); o += B
-            flags = w[o:o + B].copy(); o += B
-            slots = w[o:o + B].copy(); o += B
-            out.append(dict(round=int(h[0]), iter=int(h[1]), n0=int(h[2]), n1=int(h[3]),
-                            goal_j=int(h[4]), goal_slot=int(h[5]), end=int(h[6]),
-                            c_best_before=float(h[7:8].view(np.float32)[0]),
-                            c_best_after=float(h[8:9].view(np.float32)[0]),
-                            survivors=int(h[9]), targets=targets.copy(), parents=parents,
-                            controls=controls.copy(), xnew=xnew.copy(), cnew=cnew, flags=flags,
-                            slots=slots))
-        return out
+        return decode_trace(words, n_iters, self.K, self.B, self.d, self.m)
+
+
+def _copy_tree(call, d: int, m: int):
+    """Node-major tree of a plan or batch query through a pakr_*copy_tree call."""
+    n = C.c_int(0)
+    call(None, None, None, None, 0, C.byref(n))
+    nn = n.value
+    states = np.zeros((nn, d), np.float32)
+    actions = np.zeros((nn, m), np.float32)
+    parents = np.zeros(nn, np.int32)
+    costs = np.zeros(nn, np.float32)
+    call(_fp(states), _fp(actions), parents.ctypes.data_as(C.POINTER(C.c_int)), _fp(costs), nn,
+         C.byref(n))
+    return states, actions, parents, costs
+
+
+def decode_trace(words: np.ndarray, n_iters: int, K: int, B: int, d: int, m: int) -> list:
+    """Decode n_iters trace records (int32 words, layout of pakr_expand in pakr.h)."""
+    per = TRACE_HDR_WORDS + K * d + K + B * m + B * d + 3 * B
+    out = []
+    for i in range(n_iters):
+        w = words[i * per:(i + 1) * per]
+        h = w[:TRACE_HDR_WORDS]
+        o = TRACE_HDR_WORDS
+        f32 = lambda a: a.view(np.float32)
+        targets = f32(w[o:o + K * d]).reshape(K, d); o += K * d
+        parents = w[o:o + K].copy(); o += K
+        controls = f32(w[o:o + B * m]).reshape(B, m); o += B * m
+        xnew = f32(w[o:o + B * d]).reshape(B, d); o += B * d
+        cnew = f32(w[o:o + B]).copy(); o += B
+        flags = w[o:o + B].copy(); o += B
+        slots = w[o:o + B].copy(); o += B
+        out.append(dict(round=int(h[0]), iter=int(h[1]), n0=int(h[2]), n1=int(h[3]),
+                        goal_j=int(h[4]), goal_slot=int(h[5]), end=int(h[6]),
+                        c_best_before=float(h[7:8].view(np.float32)[0]),
+                        c_best_after=float(h[8:9].view(np.float32)[0]),
+                        survivors=int(h[9]), targets=targets.copy(), parents=parents,
+                        controls=controls.copy(), xnew=xnew.copy(), cnew=cnew, flags=flags,
+                        slots=slots))
+    return out
+
+
+def set_barrier_timeout(ms: float):
+    """Grid-barrier wait limit of later launches (ms <= 0: the default 2000 ms)."""
+    _check(load().pakr_set_barrier_timeout(float(ms)), None)
 
 
 def _bcheck(rc: int, handle=None):
@@ -490,6 +515,30 @@ class BatchPlan:
     def replan(self, budget_ms: float = 0.0, max_rounds: int = 0, max_iters: int = 0):
         _bcheck(load().pakr_batch_replan(self.h, float(budget_ms), int(max_rounds),
                                          int(max_iters)), self.h)
+
+    def expand(self, n_iters: int, trace: bool = False):
+        """Run n_iters iterations of every query in one launch; with trace=True
+        return, per query, the decoded records (as Plan.expand)."""
+        n = self.n
+        bufs, nbytes = [], []
+        if trace:
+            for q in range(n):
+                nb = int(load().pakr_batch_trace_bytes(self.h, q, n_iters))
+                bufs.append(self.torch.zeros(nb // 4, dtype=self.torch.int32, device=self.device))
+                nbytes.append(nb)
+        ptrs = (C.c_void_p * n)(*[b.data_ptr() for b in bufs]) if trace else None
+        sizes = (C.c_size_t * n)(*nbytes) if trace else None
+        _bcheck(load().pakr_batch_expand(self.h, int(n_iters), ptrs, sizes), self.h)
+        if not trace:
+            return None
+        self.torch.cuda.synchronize(self.device)
+        return [decode_trace(b.cpu().numpy(), n_iters, p.K, p.B, p.d, p.m)
+                for b, p in zip(bufs, self.probs)]
+
+    def copy_tree(self, q: int):
+        p = self.probs[q]
+        return _copy_tree(lambda *a: _bcheck(load().pakr_batch_copy_tree(self.h, q, *a), self.h),
+                          p.d, p.m)
 
     def graph_capture(self, budget_ms: float = 0.0, max_rounds: int = 0, max_iters: int = 0):
         _bcheck(load().pakr_batch_graph_capture(self.h, float(budget_ms), int(max_rounds),

@@ -17,6 +17,12 @@ import oracle
 from paper_2607_03987_amd import pakr
 
 REL_TOL = 1e-4
+# Refinement: dJ/dU of the float32 adjoint against the FP64 complex-step
+# gradient (relative L2 norm of the difference), and the checkpointed states
+# of a multi-edge rollout against the FP64 rollout (per component, relative to
+# max(1, |x|), the planner's state tolerance).
+GRAD_TOL = 1e-4
+CKPT_TOL = 1e-4
 
 
 def rel_err(a, b):

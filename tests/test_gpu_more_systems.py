@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 from paper_2607_03987_amd import pakr, refine, workloads as W
-from tests.parity import rel_err, step_parity
+from tests.parity import CKPT_TOL, GRAD_TOL, rel_err, step_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -88,13 +88,15 @@ def test_forward_and_adjoint_match_oracle(name, T, M):
         for e in range(M):
             traj = oracle.rollout(cp, states[-1], U[p, e].astype(np.float64), T, float(prob.dt))
             states.extend(traj[1:])
-        assert rel_err(ckpt[p], np.array(states)).max() <= 1e-3, p
+        ck_err = rel_err(ckpt[p], np.array(states)).max()
+        print(f"  traj {p}: checkpoint states max rel err {ck_err:.2e}", flush=True)
+        assert ck_err <= CKPT_TOL, (p, ck_err)
         go = oracle.traj_grad(cp, rp, x, U[p].astype(np.float64))
         err = np.linalg.norm(gU[p] - go) / max(np.linalg.norm(go), 1e-12)
         cos = float((gU[p] * go).sum() / (np.linalg.norm(gU[p]) * np.linalg.norm(go) + 1e-30))
         print(f"  traj {p}: J {J[p]:.6g} oracle {Jo:.6g}; grad rel L2 {err:.2e} cos {cos:.8f}",
               flush=True)
-        assert err <= 2e-3 and cos >= 0.99999, (p, err, cos)
+        assert err <= GRAD_TOL and cos >= 0.99999, (p, err, cos)
     ref.close()
 
 

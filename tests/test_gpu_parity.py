@@ -33,6 +33,26 @@ def test_step_parity(cfg, kw, iters):
     assert sum(s["valid"] for s in stats) > 0
 
 
+@pytest.mark.parametrize("cfg,kw,iters", [
+    # the paper's own rule: c_new + ||pos(x_new) - x_goal|| < c_best (Alg. 1, Sec. IV)
+    ("c1", dict(h_kind=W.H_PAPER_LITERAL, c0=14.0), 14),
+    ("c2", dict(B=1024, A=8, n_cap=40000, h_kind=W.H_PAPER_LITERAL, c0=16.0), 8),
+    # h = 0: the bound alone prunes (c_new < c_best)
+    ("c1", dict(h_kind=W.H_NONE, c0=3.0), 14),
+    ("c2", dict(B=1024, A=8, n_cap=40000, h_kind=W.H_NONE, c0=4.0), 8),
+])
+def test_step_parity_prune_rules(cfg, kw, iters):
+    """Finite initial bounds under the literal heuristic and under h = 0: the
+    prune flags must agree on every valid candidate, and the bound must both
+    keep and reject candidates over the run."""
+    prob = W.CONFIGS[cfg](**kw)
+    print(f"case {prob.name} h_kind {prob.h_kind} c0 {prob.c0}", flush=True)
+    stats = step_parity(prob, iters, log=_log)
+    valid = sum(s["valid"] for s in stats)
+    kept = sum(s["kept"] for s in stats)
+    assert 0 < kept < valid, (kept, valid)
+
+
 @pytest.mark.parametrize("kw", [
     dict(B=300, A=3, n_cap=5000),          # ragged: B not a multiple of 256, K = 100
     dict(B=8, A=8, n_cap=2000),            # K = 1

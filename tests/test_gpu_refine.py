@@ -18,7 +18,7 @@ import pytest
 
 import oracle
 from paper_2607_03987_amd import pakr, refine, workloads as W
-from tests.parity import rel_err
+from tests.parity import CKPT_TOL, GRAD_TOL, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -76,13 +76,16 @@ def test_forward_and_adjoint_match_oracle(cfg, T, M, spread):
         states = np.array(states)
         if prob.system == W.CAR:
             assert np.abs(states[:, 4]).max() < 1.0
-        assert rel_err(ckpt[p], states).max() <= 1e-3, p
+        ck_err = rel_err(ckpt[p], states).max()
+        print(f"  traj {p}: checkpoint states max rel err {ck_err:.2e} over {M * T} steps",
+              flush=True)
+        assert ck_err <= CKPT_TOL, (p, ck_err)
         go = oracle.traj_grad(cp, rp, x0[p].astype(np.float64), U[p].astype(np.float64))
         err = np.linalg.norm(gU[p] - go) / max(np.linalg.norm(go), 1e-12)
         cos = float((gU[p] * go).sum() / (np.linalg.norm(gU[p]) * np.linalg.norm(go) + 1e-30))
         print(f"  traj {p}: J {J[p]:.6g} oracle {Jo:.6g}; grad rel L2 {err:.2e} cos {cos:.8f}",
               flush=True)
-        assert err <= 2e-3 and cos >= 0.99999, (p, err, cos)
+        assert err <= GRAD_TOL and cos >= 0.99999, (p, err, cos)
     ref.close()
 
 
@@ -103,7 +106,7 @@ def test_adjoint_edge_sizes(T, M):
     for p in range(3):
         go = float(gJ[p]) * oracle.traj_grad(cp, rp, x0[p].astype(np.float64),
                                              U[p].astype(np.float64))
-        assert np.linalg.norm(gU[p] - go) <= 1e-3 * np.linalg.norm(go), p
+        assert np.linalg.norm(gU[p] - go) <= GRAD_TOL * np.linalg.norm(go), p
     ref.close()
 
 
@@ -124,7 +127,7 @@ def test_many_trajectories_sampled():
         Jo = oracle.traj_cost(cp, rp, x0[p].astype(np.float64), U[p].astype(np.float64))
         go = oracle.traj_grad(cp, rp, x0[p].astype(np.float64), U[p].astype(np.float64))
         assert abs(J[p] - Jo) <= 2e-4 * max(abs(Jo), 1.0)
-        assert np.linalg.norm(gU[p] - go) <= 2e-3 * np.linalg.norm(go)
+        assert np.linalg.norm(gU[p] - go) <= GRAD_TOL * np.linalg.norm(go)
     ref.close()
 
 
@@ -246,8 +249,9 @@ def test_refine_never_raises_j_and_keeps_controls_in_the_box():
     assert np.all(J1 <= J0) and np.mean(J1 < 0.9 * J0) > 0.5
     Ur = res["U_refined"].cpu().numpy()
     assert np.all(Ur >= -1.0) and np.all(Ur <= 1.0)
-    # J_after is the objective of the returned controls (oracle, FP64)
-    for p in range(0, n, 5):
+    # J_after is the objective of the returned controls (oracle, FP64), for
+    # every trajectory -- including those whose controls straddle a wave
+    for p in range(n):
         Jo = oracle.traj_cost(cp, rp, x0[p].cpu().numpy().astype(np.float64),
                               Ur[p].astype(np.float64))
         assert abs(J1[p] - Jo) <= 2e-4 * max(abs(Jo), 1.0)
