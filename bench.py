@@ -254,8 +254,9 @@ def other_systems_leg(torch, pakr, W, budget_ms, seeds):
         w.replan(budget_ms=min(budget_ms, 20.0))
         torch.cuda.synchronize()
         w.close()
-        exp = pairs = 0
+        exp = pairs = iters = 0
         ms, t_first = [], []
+        steps = [0.0] * 6
         for sd in range(seeds):
             prob = mk(seed=sd)
             pl = pakr.Plan(prob)
@@ -268,6 +269,8 @@ def other_systems_leg(torch, pakr, W, budget_ms, seeds):
             ms.append(e0.elapsed_time(e1))
             exp += st["expansions"]
             pairs += st["nn_pairs"]
+            iters += st["total_iters"]
+            steps = [a + b for a, b in zip(steps, st["step_ms"])]
             if sols:
                 t_first.append(sols[0]["t_ms"])
             pl.close()
@@ -278,6 +281,8 @@ def other_systems_leg(torch, pakr, W, budget_ms, seeds):
                      "time_to_first_ms_median": statistics.median(t_first) if t_first else None,
                      "solved": f"{len(t_first)}/{seeds}", "B": prob.B, "A": prob.A, "T": prob.T,
                      "kernel_ms_mean": statistics.mean(ms),
+                     "us_per_iteration": 1e3 * sum(ms) / max(iters, 1),
+                     "step_us_per_iteration": step_split(steps, iters),
                      "roofline": {"bound": "alu", "achieved": tf,
                                   "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                                   "frac": tf / FP32_VECTOR_PEAK_TFLOPS}}
@@ -321,21 +326,138 @@ def saturating_rollout_leg(torch, pakr, W, iters, B=65536, A=16):
     return out
 
 
-def cpu_baseline(prob, seconds):
-    """Time the FP64 reference (single thread) on the same query for ~`seconds`."""
+def aox_leg(torch, pakr, make, seeds, budget_ms, lanes=0, wg_per_cu=0):
+    """AO-x queries of one workload, one per seed (each its own scene and
+    Philox key), each a single launch with a device-clock budget: the medians
+    of Table 2's columns -- time to the first solution and its cost, time of
+    the last improvement within the budget and the final cost -- over the
+    solved seeds, the success rate, and expansions/s from the launches' own
+    event timing."""
+    stream = torch.cuda.current_stream()
+    w = pakr.Plan(make(10_000), lanes=lanes, wg_per_cu=wg_per_cu)
+    w.replan(budget_ms=min(budget_ms, 20.0))
+    torch.cuda.synchronize()
+    w.close()
+    t1, c1, tf, cf, ms, exp, iters = [], [], [], [], [], 0, 0
+    steps = [0.0] * 6
+    for sd in seeds:
+        prob = make(sd)
+        pl = pakr.Plan(prob, lanes=lanes, wg_per_cu=wg_per_cu)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        pl.replan(budget_ms=budget_ms)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        st, sols = pl.status(), pl.solutions()
+        ms.append(e0.elapsed_time(e1))
+        exp += st["expansions"]
+        iters += st["total_iters"]
+        steps = [a + b for a, b in zip(steps, st["step_ms"])]
+        if sols:
+            t1.append(sols[0]["t_ms"])
+            c1.append(sols[0]["cost"])
+            tf.append(sols[-1]["t_ms"])
+            cf.append(sols[-1]["cost"])
+        pl.close()
+    med = lambda v: statistics.median(v) if v else None
+    prob = make(seeds[0])
+    return {"workload": prob.name, "B": prob.B, "A": prob.A, "T": prob.T, "n_cap": prob.n_cap,
+            "budget_ms": budget_ms, "seeds": f"{seeds[0]}..{seeds[-1]}",
+            "solved": f"{len(t1)}/{len(seeds)}",
+            "time_first_ms_median": med(t1), "cost_first_median": med(c1),
+            "time_final_ms_median": med(tf), "cost_final_median": med(cf),
+            "expansions_per_s": exp / (sum(ms) / 1e3),
+            "us_per_iteration": 1e3 * sum(ms) / max(iters, 1),
+            "step_us_per_iteration": step_split(steps, iters)}
+
+
+STEP_NAMES = ["nn_scan", "barrier_a", "parent_reduce", "rollout", "barrier_b", "insert"]
+
+
+def step_split(step_ms, iters):
+    """Device time per iteration of each step of the loop (workgroup 0's clock)."""
+    return {k: round(1e3 * v / max(iters, 1), 3) for k, v in zip(STEP_NAMES, step_ms)}
+
+
+def host_cpu():
+    """The host's CPU model, logical CPUs and the CPUs this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"model": model, "nproc": os.cpu_count(), "usable": usable}
+
+
+def _oracle_run(job):
+    """Worker: `iters` iterations of the FP64 reference on workload c2, seed
+    `seed`; returns its wall time and end state (run in a fresh process)."""
+    seed, iters = job
     import oracle
+    from paper_2607_03987_amd import workloads as W
+    orc = oracle.OraclePlan(W.config_c2(seed=seed))
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        orc.iterate(report=False)
+    dt = time.perf_counter() - t0
+    st = orc.state()
+    sols = [(s["round"], s["iter"], s["node"], s["cost"]) for s in orc.solutions()]
+    return {"seed": seed, "seconds": dt, "expansions": st["expansions"], "n": st["n"],
+            "n_solutions": st["n_solutions"], "solutions": sols}
+
+
+def cpu_baseline(seconds, max_workers=16):
+    """The FP64 reference on this host's cores, before the GPU is touched.
+
+    One thread first runs workload c2 (seed 0) for about `seconds`; then one
+    process per usable core (at most `max_workers`, the host share of one
+    GPU) runs the same number of iterations on seeds 0, 1, ..., all at once.
+    Worker 0 replays the single-thread run and must end in the same state
+    (the reference is deterministic).  `value` is the all-core rate."""
+    import multiprocessing as mp
+
+    import oracle
+    from paper_2607_03987_amd import workloads as W
+    prob = W.config_c2(seed=0)
     orc = oracle.OraclePlan(prob)
     t0 = time.perf_counter()
     iters = 0
     while time.perf_counter() - t0 < seconds:
         orc.iterate(report=False)
         iters += 1
-    dt = time.perf_counter() - t0
+    dt1 = time.perf_counter() - t0
     st = orc.state()
-    return {"value": st["expansions"] / dt, "unit": "expansions/s", "cores": 1, "kind": "oracle",
-            "sample": f"{prob.name} seed {prob.seed}: first {iters} iterations "
-                      f"({st['expansions']} expansions, {st['n_solutions']} solution(s), "
-                      f"tree {st['n']} nodes) in {dt:.1f} s, FP64, one host thread"}
+    one = {"value": st["expansions"] / dt1, "iterations": iters, "seconds": dt1,
+           "expansions": st["expansions"], "tree_nodes": st["n"],
+           "solutions": st["n_solutions"]}
+    host = host_cpu()
+    workers = max(1, min(max_workers, host["usable"] or 1))
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        res = pool.map(_oracle_run, [(sd, iters) for sd in range(workers)])
+    wall = time.perf_counter() - t0
+    r0 = res[0]
+    same = (r0["expansions"] == st["expansions"] and r0["n"] == st["n"] and
+            r0["solutions"] == [(s["round"], s["iter"], s["node"], s["cost"])
+                                for s in orc.solutions()])
+    total = sum(r["expansions"] for r in res)
+    return {"value": total / wall, "unit": "expansions/s", "cores": workers, "kind": "oracle",
+            "sample": f"{prob.name}: {workers} processes, seeds 0..{workers - 1}, {iters} "
+                      f"iterations each ({total} expansions) in {wall:.1f} s wall, FP64; the "
+                      f"single-thread run of seed 0 did the same {iters} iterations "
+                      f"({st['expansions']} expansions, {st['n_solutions']} solution(s), tree "
+                      f"{st['n']} nodes) in {dt1:.1f} s",
+            "single_thread": one, "worker0_identical_to_single_thread": same,
+            "host": host}
 
 
 def main():
@@ -358,9 +480,22 @@ def main():
     ap.add_argument("--other-systems-ms", type=float, default=100.0)
     ap.add_argument("--other-systems-seeds", type=int, default=3)
     ap.add_argument("--no-saturating-rollout", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the per-configuration AO-x legs (Table 2's columns)")
+    ap.add_argument("--c1-seeds", type=int, default=100)
+    ap.add_argument("--c1-budget-ms", type=float, default=50.0)
+    ap.add_argument("--c2-seeds", type=int, default=100)
+    ap.add_argument("--c3-seeds", type=int, default=20)
+    ap.add_argument("--c3-budget-ms", type=float, default=200.0)
+    ap.add_argument("--c4-seeds", type=int, default=10)
+    ap.add_argument("--c4-budget-ms", type=float, default=500.0)
     ap.add_argument("--saturating-iters", type=int, default=50)
     ap.add_argument("--refine-budget-ms", type=float, default=500.0)
     ap.add_argument("--refine-paths", type=int, default=256)
+    ap.add_argument("--maps-out", default="",
+                    help="after the run (every plan closed, the device synchronized) write "
+                         "/proc/self/maps to this file, to place the frames of any exit-time "
+                         "fault")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before timing, run one plain device copy of this size (a known-size "
                          "kernel against which HBM counters are scaled)")
@@ -369,6 +504,10 @@ def main():
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the planner runs "
               "on a single GPU and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
+
+    # the FP64 reference first, in fresh worker processes, before this
+    # process touches the GPU
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_seconds)
 
     import torch
 
@@ -483,6 +622,7 @@ def main():
         "refinement": None,
         "other_systems": None,
         "saturating_rollout": None,
+        "configs": None,
     }
     for p in plans:
         p.close()
@@ -499,9 +639,27 @@ def main():
                                                  args.other_systems_seeds)
     if not args.no_saturating_rollout:
         out["saturating_rollout"] = saturating_rollout_leg(torch, pakr, W, args.saturating_iters)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(W.config_c2(seed=0), args.cpu_seconds)
+    if not args.no_configs:
+        out["configs"] = {
+            "c1": aox_leg(torch, pakr, lambda sd: W.config_c1(seed=sd), list(range(args.c1_seeds)),
+                          args.c1_budget_ms),
+            "c2": aox_leg(torch, pakr, lambda sd: W.config_c2(seed=sd), list(range(args.c2_seeds)),
+                          args.budget_ms, lanes=lanes, wg_per_cu=wgpc),
+            "c3": aox_leg(torch, pakr, lambda sd: W.config_c3(seed=sd), list(range(args.c3_seeds)),
+                          args.c3_budget_ms),
+            "c4": aox_leg(torch, pakr, lambda sd: W.config_c4(seed=sd), list(range(args.c4_seeds)),
+                          args.c4_budget_ms),
+        }
+    out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
+    # every plan, batch and refiner above is closed; leave nothing queued on
+    # the device for the interpreter's teardown
+    import gc
+    gc.collect()
+    torch.cuda.synchronize()
+    if args.maps_out:
+        with open("/proc/self/maps") as src, open(args.maps_out, "w") as dst:
+            dst.write(src.read())
 
 
 if __name__ == "__main__":

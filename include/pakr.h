@@ -162,6 +162,17 @@ typedef struct pakr_params {
                                       obstacle tests; 0 = auto (from the obstacle count) */
   int workgroups_per_cu;           /* with grid = 0: launch this many workgroups per CU
                                       and reserve LDS so that no CU holds more; 0 = 1    */
+  int spec_tiles;                  /* NN tiles each workgroup without a rollout chunk scans
+                                      ahead for the next iteration while the others roll
+                                      out (the tree is frozen then; results do not depend
+                                      on it): 0 = auto, -1 = none, else 1..1024          */
+  int tier0_nodes;                 /* first tier of the tree (Sec. IV-A's memory tiers): while
+                                      a round's tree has at most this many nodes, one
+                                      workgroup runs each iteration alone and the grid takes
+                                      over beyond it (results do not depend on it); 0 = auto
+                                      (a power of 4 from the query's sizes), -1 = none.
+                                      Single-query plans only: a batch's team always plans
+                                      together                                            */
 } pakr_params;
 
 typedef struct pakr_stats {

@@ -275,6 +275,8 @@ std::string validate(const pakr_system* s, const pakr_scene* sc, const float* x0
       p->lanes_per_candidate != 4 && p->lanes_per_candidate != 8 && p->lanes_per_candidate != 16)
     return "lanes_per_candidate must be 0, 1, 2, 4, 8 or 16";
   if (p->workgroups_per_cu < 0 || p->workgroups_per_cu > 8) return "workgroups_per_cu must be 0..8";
+  if (p->spec_tiles < -1 || p->spec_tiles > 1024) return "spec_tiles must be -1..1024";
+  if (p->tier0_nodes < -1) return "tier0_nodes must be >= -1";
   m = validate_scene(sc);
   if (!m.empty()) return m;
   *code = PAKR_E_GOAL_INVALID;
@@ -331,6 +333,37 @@ int nn_tpg_for(int K, int qt) {
   return t;
 }
 
+// Tiles each idle workgroup scans ahead during the rollout phase (0: none).
+// Auto: about as many tiles as one workgroup scans in the time the rollout
+// phase takes -- a tile costs ~K (2d + 1) cycles of one CU (d subtractions
+// and d FMAs per target and node, 64 nodes over 64 lanes), the rollout ~4
+// cycles per instruction of a lane's serial chain per resident rollout wave,
+// plus the wait for the slowest chunk.
+int spec_tiles_for(const pakr_params& prm, const DevProblem& Q, int n_obs) {
+  if (prm.spec_tiles < 0 || Q.G <= Q.G_roll) return 0;
+  if (prm.spec_tiles > 0) return prm.spec_tiles;
+  const double tile = (double)Q.K * (2.0 * Q.d + 1.0);
+  const double chain =
+      (double)Q.T * (12.0 * Q.d + 4.0 * f_eval_of(Q.system) + 3.0 * Q.npos * n_obs / Q.lanes);
+  const double waves = std::max(1.0, (double)(Q.cpb * Q.lanes) / (4.0 * WAVE));
+  const double roll = chain * 4.0 * waves + 4000.0;
+  return std::max(1, std::min(64, (int)(roll / tile)));
+}
+
+// The first tier of the tree (0: none): the largest of the paper's tier
+// sizes 4^k, k = 4..8, whose NN scan one workgroup does in about 20 000
+// cycles (K targets x n nodes x (2d + 1) instructions over 64 lanes), and
+// only when one rollout pass of the workgroup takes the whole batch.
+int tier0_nodes_for(const pakr_params& prm, const DevProblem& Q) {
+  if (prm.tier0_nodes < 0 || Q.G <= 1) return 0;
+  if (prm.tier0_nodes > 0) return prm.tier0_nodes;
+  if (Q.G_roll > 1) return 0;
+  int t = 0;
+  for (int k = 4, v = 256; k <= 8; ++k, v *= 4)
+    if ((double)Q.K * v * (2.0 * Q.d + 1.0) / WAVE <= 20000.0) t = v;
+  return t;
+}
+
 // The device record of one query planned by G workgroups with L lanes per candidate.
 DevProblem make_problem(const pakr_system& sys, const pakr_scene& scene, const pakr_goal& goal,
                         const pakr_params& prm, int G, int lanes, int rt = NT, int qt = 1) {
@@ -356,6 +389,8 @@ DevProblem make_problem(const pakr_system& sys, const pakr_scene& scene, const p
   Q.cpb = rt / lanes;
   Q.nn_tpg = nn_tpg_for(Q.K, qt);
   Q.G_roll = (prm.B + Q.cpb - 1) / Q.cpb;
+  Q.spec_tiles = spec_tiles_for(prm, Q, scene.n_box + scene.n_sphere);
+  Q.tier0_nodes = tier0_nodes_for(prm, Q);
   Q.max_path_edges = prm.max_path_edges > 0 ? prm.max_path_edges : DEFAULT_PATH_EDGES;
   Q.obs_floats = obs_floats_of(P, scene.n_box, scene.n_sphere);
   Q.key0 = (uint32_t)(prm.seed & 0xffffffffull);
@@ -1086,6 +1121,8 @@ int pakr_batch_init(int n, const pakr_system* sys, const pakr_scene* scenes,
   return PAKR_OK;
 }
 
+}  // extern "C"
+
 namespace {
 
 // Upload `table` (one record per query) to `d_table`; syncs the batch stream.
@@ -1142,6 +1179,8 @@ int batch_header(pakr_batch* bt, int q, DevHeader* h) {
 }
 
 }  // namespace
+
+extern "C" {
 
 int pakr_batch_replan(pakr_batch* bt, double budget_ms, int max_rounds, long long max_iters) {
   if (!bt) return PAKR_E_INVALID_ARG;
@@ -1314,6 +1353,7 @@ struct pakr_refiner {
   size_t shmem = 0;
   std::string err;
 };
+
 
 namespace {
 

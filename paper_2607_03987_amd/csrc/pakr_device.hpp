@@ -32,7 +32,10 @@ struct DevProblem {
   int n_box, n_sph, G, G_roll;
   int max_path_edges, obs_floats;
   int lanes, cpb;                  // lanes per candidate, candidates per rollout workgroup
-  int nn_tpg, pad_i;              // NN: threads per node group (NT / TPG groups)
+  int nn_tpg;                     // NN: threads per node group (NT / TPG groups)
+  int spec_tiles;                 // tiles each idle workgroup scans ahead in phase 2 (0: none)
+  int tier0_nodes;                // workgroup 0 plans alone while the tree has <= this many nodes
+  int pad_t;
   uint32_t key0, key1;
   float dt, h_speed, c0, vnorm_max;
   float goal_r, goal_r2, edge_duration, pad0;
@@ -56,7 +59,12 @@ struct DevHeader {
   int best_edges, best_node, pad0, pad1;
   float best_cost, pad2, pad3, pad4;
   uint32_t release;                          // barrier release word
-  int pad5[3];
+  // hand-off of the loop from workgroup 0 (alone while the tree is in the
+  // first tier) to the grid: word ((iterations done + 1) << 1 | call ended),
+  // then the loop state that the resuming workgroups adopt
+  uint32_t join;
+  int ho_rounds, ho_status;
+  uint32_t ho_gen;
   long long ticks[8];                        // per-step device time of the last call
 };
 

@@ -215,6 +215,8 @@ struct Books {
   int c_sol;
 };
 
+struct LoopState;
+
 // LDS used by one query's loop; each kernel that runs plan_loop declares it.
 struct Smem {
   float* obs;                  // dynamic: obstacles (see any_obstacle_hit)
@@ -229,14 +231,93 @@ struct Smem {
   int* fail;
   int* misc;                   // [2]
   Books* books;
+  LoopState* state;            // hand-off state read by waiting workgroups
 };
 
-// The AO-x loop of one query, run by workgroup `b` of the `G` workgroups that
-// share the query (G = 1 when a workgroup plans a query alone).  QT targets
-// per thread in the NN scan; GROUPED: the scan may split tiles into node
-// slices (P.nn_tpg threads per slice), else one target per thread (QT = 1).
-template <int SYS, int QT, bool GROUPED>
-__device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int G, const Smem& sm) {
+// Loop state handed from workgroup 0 to the rest of a query's workgroups
+// when the tree leaves the first tier (see plan_loop).
+struct LoopState {
+  int n, round, iter, n_sol, rounds_done, status;
+  float c_best;
+  uint32_t gen;
+  long long it_done;
+  int ended;
+};
+
+// Workgroup 0 publishes the loop state; the resuming workgroups take the
+// next iteration (iterations done = it_done) from it, or leave if `ended`.
+// Every thread of the workgroup calls it.
+__device__ __forceinline__ void publish_handoff(const KArgs& a, const LoopState& st) {
+  __syncthreads();  // the whole workgroup's writes precede the release below
+  if (threadIdx.x == 0) {
+    DevHeader* h = a.hdr;
+    h->n = st.n;
+    h->round = st.round;
+    h->iter = st.iter;
+    h->n_solutions = st.n_sol;
+    h->c_best = st.c_best;
+    h->ho_rounds = st.rounds_done;
+    h->ho_status = st.status;
+    h->ho_gen = st.gen;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const uint32_t w = ((uint32_t)(st.it_done + 1) << 1) | (uint32_t)(st.ended != 0);
+    __hip_atomic_store(&h->join, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// A workgroup other than 0, which stopped at iteration `waited_at`, waits
+// until workgroup 0 publishes a hand-off made at or after it, and adopts
+// its state.  Returns false if the wait passed `deadline` (device clock).
+__device__ __forceinline__ bool await_handoff(const KArgs& a, long long waited_at,
+                                              long long deadline, LoopState* s_st) {
+  if (threadIdx.x == 0) {
+    bool ok = true;
+    uint32_t w;
+    while (true) {
+      w = __hip_atomic_load(&a.hdr->join, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if ((long long)(w >> 1) > waited_at) break;
+      if (wall_clock64() > deadline) {
+        ok = false;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (ok) {
+      const DevHeader* h = a.hdr;
+      s_st->n = h->n;
+      s_st->round = h->round;
+      s_st->iter = h->iter;
+      s_st->n_sol = h->n_solutions;
+      s_st->c_best = h->c_best;
+      s_st->rounds_done = h->ho_rounds;
+      s_st->status = h->ho_status;
+      s_st->gen = h->ho_gen;
+      s_st->it_done = (long long)(w >> 1) - 1;
+      s_st->ended = (int)(w & 1u);
+    } else {
+      s_st->ended = -1;
+    }
+  }
+  __syncthreads();
+  return s_st->ended >= 0;
+}
+
+// The AO-x loop of one query, run by workgroup `b` of the `G_all` workgroups
+// that share the query (G_all = 1 when a workgroup plans a query alone).  QT
+// targets per thread in the NN scan; GROUPED: the scan may split tiles into
+// node slices (P.nn_tpg threads per slice), else one target per thread.
+//
+// Tiers (the paper's memory tiers of the tree, Sec. IV-A): while the round's
+// tree has at most P.tier0_nodes nodes, workgroup 0 runs every step of the
+// iteration alone (G = 1: no grid barrier, no hand-over through memory
+// between workgroups) and the others wait; once it outgrows that tier, the
+// whole grid takes over from the state workgroup 0 hands over.  At a round
+// end that returns to the first tier, a grid barrier first puts every
+// workgroup's writes in memory, so workgroup 0 can reuse the slots alone.
+template <int SYS, int QT, bool GROUPED, bool TIERED>
+__device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int G_all,
+                                          const Smem& sm) {
   static_assert(GROUPED || QT == 1, "an ungrouped scan holds one target per thread");
   constexpr int D = Sys<SYS>::D, M = Sys<SYS>::M, NP = Sys<SYS>::P;
   const DevProblem& P = a.P;
@@ -276,6 +357,7 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
   int n_sol = a.hdr->n_solutions;
   long long it_done = 0, rounds_done = 0;
   int status = 0;
+  int spec_lo = 0;  // tiles [0, spec_lo) already scanned for this iteration's targets
 
   // workgroup-0 bookkeeping, kept by its thread 0 in LDS
   Books& bk = *sm.books;
@@ -298,70 +380,108 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
     bk.c_exp = bk.c_ins = bk.c_nn = 0;
     bk.c_sol = 0;
   }
-  // both NN key buffers start cleared
-  for (int k = b * NT + tid; k < 2 * K; k += G * NT) store_through(&a.nn_keys[k], ~0ull);
-  if (!grid_barrier(a, gen, &s_fail, b, G)) {
+  // both NN key buffers start cleared, and no hand-off is pending
+  for (int k = b * NT + tid; k < 2 * K; k += G_all * NT) store_through(&a.nn_keys[k], ~0ull);
+  if (b == 0 && tid == 0) store_through(&a.hdr->join, 0u);
+  if (!grid_barrier(a, gen, &s_fail, b, G_all)) {
     if (tid == 0) __hip_atomic_store(&a.hdr->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return;
   }
+  const int tier0 = (TIERED && G_all > 1) ? P.tier0_nodes : 0;
+  // a waiting workgroup gives up at the call's guard time
+  const long long wait_deadline = wall_clock64() + a.guard_ticks;
+  LoopState* const s_st = sm.state;
 
   while (true) {
     if (a.max_iters > 0 && it_done >= a.max_iters) { status |= PAKR_S_ITERS_DONE; break; }
     if (a.max_rounds > 0 && rounds_done >= a.max_rounds) { status |= PAKR_S_ROUNDS_DONE; break; }
+    // first tier: workgroup 0 alone (identical decision in every workgroup)
+    const bool solo = TIERED && n <= tier0;
+    if (solo && b != 0) {
+      if (!await_handoff(a, it_done, wait_deadline, s_st)) {
+        if (tid == 0) __hip_atomic_store(&a.hdr->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+      }
+      if (s_st->ended) return;  // workgroup 0 writes the call's results
+      // the same values in every lane: keep the loop state in scalar registers
+      auto uni = [](int v) { return __builtin_amdgcn_readfirstlane(v); };
+      n = uni(s_st->n);
+      round = uni(s_st->round);
+      iter = uni(s_st->iter);
+      n_sol = uni(s_st->n_sol);
+      c_best = __int_as_float(uni(__float_as_int(s_st->c_best)));
+      rounds_done = uni(s_st->rounds_done);
+      status = uni(s_st->status);
+      gen = (uint32_t)uni((int)s_st->gen);
+      it_done = (long long)uni((int)s_st->it_done);
+      spec_lo = 0;
+      continue;
+    }
+    const int G = solo ? 1 : G_all;
     int* trace = (a.trace != nullptr && it_done < a.trace_iters) ? a.trace + it_done * a.trace_words
                                                                  : nullptr;
-    const int ntiles = (n + TILE - 1) / TILE;
-    const int G_act = min(G, ntiles);
+    const int n0 = n;
+    const int ntiles = (n0 + TILE - 1) / TILE;
     // this iteration's NN keys: every scanning workgroup folds its minima in
     // by device-scope atomic min; two buffers alternate, each cleared during
     // the insertion phase of the iteration that consumed it
     unsigned long long* const nnk = a.nn_keys + (size_t)(it_done & 1) * K;
+    unsigned long long* const nnk_next = a.nn_keys + (size_t)((it_done + 1) & 1) * K;
     if (keeper) bk.tk_mark = wall_clock64();
 
-    // ---------------- phase 1: targets + nearest neighbour -----------------
-    // Targets are drawn once per chunk of kc <= TPG * QT and staged in LDS.
-    // Thread (grp, tl) holds the chunk's targets tl, tl + TPG, ... (QT of
+    // ---------------- NN scan (phase 1, and speculatively in phase 2) -----
+    // Scans tiles t0, t0 + tstep, ... (at most tcount of them, t < t_end) of
+    // the tree's first n0 nodes for the K targets of iteration it_q of this
+    // round.  Targets are drawn once per chunk of kc <= TPG * QT and staged in
+    // LDS; thread (grp, tl) holds the chunk's targets tl, tl + TPG, ... (QT of
     // them, so every node read from LDS serves QT targets) and scans node
-    // slice grp (TILE / NG consecutive nodes) of each tile this workgroup
-    // owns; the NG groups' keys meet in LDS by atomic min.
+    // slice grp (TILE / NG consecutive nodes) of each tile; the NG groups'
+    // keys meet in LDS by atomic min and each workgroup's per-target minimum
+    // is folded into `keys` by device-scope atomic min.  With trace_q set,
+    // workgroup 0 records the targets (drawn even if it scans nothing).
     const int TPG = GROUPED ? P.nn_tpg : NT, NG = NT / TPG, SL = TILE / NG;
-    int tid_nn = tid;
-    asm volatile("" : "+v"(tid_nn));  // derived per iteration, not held across the loop
-    const int grp = tid_nn / TPG, tl = tid_nn - grp * TPG;
-    // (one target per thread and one group: the target is drawn straight
-    // into registers and the key written straight out)
-    const bool direct = !GROUPED || (QT == 1 && NG == 1);
-    for (int base = 0; base < K; base += TPG * QT) {
-      const int kc = min(K - base, TPG * QT);
-      if (!direct) __syncthreads();  // the previous chunk's readers of s_q and s_key are done
-      for (int k = tid; k < kc && !direct; k += NT) {
-        float qs[D];
-        sample_state<D>(P, (uint32_t)(base + k), (uint32_t)iter, (uint32_t)round, qs);
+    auto nn_scan = [&](uint32_t it_q, int t0, int tstep, int tcount, int t_end,
+                       unsigned long long* keys, int* trace_q) {
+      const bool scans = tcount > 0 && t0 < t_end;
+      const bool record = trace_q != nullptr && b == 0;
+      if (!scans && !record) return;
+      int tid_nn = tid;
+      asm volatile("" : "+v"(tid_nn));  // derived per call, not held across the loop
+      const int grp = tid_nn / TPG, tl = tid_nn - grp * TPG;
+      // (one target per thread and one group: the target is drawn straight
+      // into registers and the key written straight out)
+      const bool direct = !GROUPED || (QT == 1 && NG == 1);
+      for (int base = 0; base < K; base += TPG * QT) {
+        const int kc = min(K - base, TPG * QT);
+        if (!direct) __syncthreads();  // the previous chunk's readers of s_q and s_key are done
+        for (int k = tid; k < kc && !direct; k += NT) {
+          float qs[D];
+          sample_state<D>(P, (uint32_t)(base + k), it_q, (uint32_t)round, qs);
 #pragma unroll
-        for (int c = 0; c < D; ++c) s_q[c * KCM + k] = qs[c];
-        if (trace != nullptr && b == 0) {
-          TraceView tv(trace, K, B, D, M);
+          for (int c = 0; c < D; ++c) s_q[c * KCM + k] = qs[c];
+          if (record) {
+            TraceView tv(trace_q, K, B, D, M);
 #pragma unroll
-          for (int c = 0; c < D; ++c) tv.targets[(size_t)(base + k) * D + c] = qs[c];
-        }
-        s_key[k] = ~0ull;
-      }
-      if (!direct) __syncthreads();
-      float q[QT][D];
-      if (direct) {
-        if (tid < kc) {
-          sample_state<D>(P, (uint32_t)(base + tid), (uint32_t)iter, (uint32_t)round, q[0]);
-          if (trace != nullptr && b == 0) {
-            TraceView tv(trace, K, B, D, M);
-#pragma unroll
-            for (int c = 0; c < D; ++c) tv.targets[(size_t)(base + tid) * D + c] = q[0][c];
+            for (int c = 0; c < D; ++c) tv.targets[(size_t)(base + k) * D + c] = qs[c];
           }
-        } else {
-#pragma unroll
-          for (int c = 0; c < D; ++c) q[0][c] = 0.0f;
+          s_key[k] = ~0ull;
         }
-      }
-      if (b < G_act) {
+        if (!direct) __syncthreads();
+        float q[QT][D];
+        if (direct) {
+          if (tid < kc) {
+            sample_state<D>(P, (uint32_t)(base + tid), it_q, (uint32_t)round, q[0]);
+            if (record) {
+              TraceView tv(trace_q, K, B, D, M);
+#pragma unroll
+              for (int c = 0; c < D; ++c) tv.targets[(size_t)(base + tid) * D + c] = q[0][c];
+            }
+          } else {
+#pragma unroll
+            for (int c = 0; c < D; ++c) q[0][c] = 0.0f;
+          }
+        }
+        if (!scans) continue;
         float bd[QT];
         int bi[QT];
 #pragma unroll
@@ -374,9 +494,9 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
           bd[qq] = INFINITY;
           bi[qq] = 0;
         }
-        // software pipeline: the next owned tile is fetched into registers
-        // while the current one is scanned from LDS.  Slots past the tree end
-        // get a coordinate whose squared distance overflows to +inf.
+        // software pipeline: the next tile is fetched into registers while
+        // the current one is scanned from LDS.  Slots past the tree end get a
+        // coordinate whose squared distance overflows to +inf.
         constexpr int PF = (D * TILE + NT - 1) / NT;
         float pre[PF];
         auto fetch = [&](int t) {
@@ -385,13 +505,14 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
           for (int r = 0; r < PF; ++r) {
             const int idx = tid + r * NT;
             const int c = idx / TILE, i = idx - c * TILE;
-            pre[r] = (idx < D * TILE && node0 + i < n) ? a.states[(size_t)c * NC + node0 + i]
-                                                       : 3.0e38f;
+            pre[r] = (idx < D * TILE && node0 + i < n0) ? a.states[(size_t)c * NC + node0 + i]
+                                                        : 3.0e38f;
           }
         };
-        fetch(b);
+        fetch(t0);
         const int i0 = grp * SL;
-        for (int t = b; t < ntiles; t += G) {
+        int t = t0;
+        for (int cnt = 0; cnt < tcount && t < t_end; ++cnt, t += tstep) {
           const int node0 = t * TILE;
           __syncthreads();
 #pragma unroll
@@ -400,7 +521,7 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
             if (idx < D * TILE) (&s_tile[0][0])[idx] = pre[r];
           }
           __syncthreads();
-          if (t + G < ntiles) fetch(t + G);
+          if (cnt + 1 < tcount && t + tstep < t_end) fetch(t + tstep);
 #pragma unroll 2
           for (int i = i0; i < i0 + SL; i += 4) {
             float4 pc[D];
@@ -430,8 +551,7 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
           }
         }
         if (direct) {
-          if (tid < kc)
-            atomicMin(&nnk[base + tid], pack_key(bd[0], (uint32_t)bi[0]));
+          if (tid < kc) atomicMin(&keys[base + tid], pack_key(bd[0], (uint32_t)bi[0]));
         } else {
 #pragma unroll
           for (int qq = 0; qq < QT; ++qq) {
@@ -443,10 +563,21 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
             }
           }
           __syncthreads();
-          for (int k = tid; k < kc; k += NT)
-            atomicMin(&nnk[base + k], s_key[k]);
+          for (int k = tid; k < kc; k += NT) atomicMin(&keys[base + k], s_key[k]);
         }
       }
+    };
+
+    // ---------------- phase 1: targets + nearest neighbour -----------------
+    // Tile t (64 nodes) belongs to workgroup t mod G, which writes it in the
+    // insertion phase and scans it here.  Tiles [0, spec_lo) were already
+    // scanned for these targets by the previous iteration's idle workgroups;
+    // a tree of the root alone needs no scan (its only node is the parent).
+    if (n0 > 1) {
+      const int t_first = spec_lo + ((b - spec_lo) % G + G) % G;
+      nn_scan((uint32_t)iter, t_first, G, INT_MAX, ntiles, nnk, trace);
+    } else {
+      nn_scan((uint32_t)iter, 0, G, 0, 0, nnk, trace);
     }
     mark(0);
     // workgroup 0 decides whether the call stops here (1: budget spent,
@@ -489,7 +620,7 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
         br = j - k * A;
         // the lanes of a candidate and the A candidates of a target read the
         // same key: one cache line serves a wave
-        parent = (int)(uint32_t)(nnk[k] & 0xffffffffull);
+        parent = n0 > 1 ? (int)(uint32_t)(nnk[k] & 0xffffffffull) : 0;
         sample_control<M>(P, (uint32_t)k, (uint32_t)br, (uint32_t)iter, (uint32_t)round, u);
 #pragma unroll
         for (int c = 0; c < D; ++c) x[c] = a.states[(size_t)c * NC + parent];
@@ -578,6 +709,18 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
       }
       mark(3);
     }
+    // Workgroups without a rollout chunk scan ahead: the tree is frozen until
+    // the insertion phase, and the next iteration's targets are fixed by their
+    // counters, so idle workgroup j scans full tiles j, j + I, ... (spec_tiles
+    // of them, I idle workgroups) for iteration iter + 1.  Together they cover
+    // the prefix [0, min(spec_tiles * I, full tiles)) of the tree, which the
+    // next phase 1 skips.  The minimum is idempotent, so results do not depend
+    // on how much is scanned ahead; if this iteration ends the round, the next
+    // one starts from the root and reads no keys.
+    const int n_idle = G - GR;
+    const bool spec_on = n_idle > 0 && P.spec_tiles > 0 && iter + 1 < P.max_iters_per_round;
+    if (spec_on && b >= GR) nn_scan((uint32_t)(iter + 1), b - GR, n_idle, P.spec_tiles,
+                                    n0 / TILE, nnk_next, nullptr);
     mark(3);
     if (!grid_barrier(a, gen, &s_fail, b, G)) {
       if (tid == 0) __hip_atomic_store(&a.hdr->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -600,7 +743,6 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
     __syncthreads();
     block_exclusive_scan(s_cnt, s_off, GR, s_wave);
     const int survivors = s_off[GR];
-    const int n0 = n;
     const int n_ins = min(survivors, P.n_cap - n0);
     const int n1 = n0 + n_ins;
     if (n_ins > 0) {
@@ -746,11 +888,31 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
       iter = 0;
       n = 1;
       ++rounds_done;
+      spec_lo = 0;
     } else {
       ++iter;
       n = n1;
+      spec_lo = spec_on ? min(P.spec_tiles * n_idle, n0 / TILE) : 0;
     }
     ++it_done;
+    if (!TIERED) {
+    } else if (solo && n > tier0) {
+      // the tree left the first tier: the grid takes the next iteration over
+      const LoopState st = {n, round, iter, n_sol, (int)rounds_done, status, c_best, gen, it_done, 0};
+      publish_handoff(a, st);
+    } else if (!solo && n <= tier0) {
+      // back to the first tier (a new round): every workgroup's writes reach
+      // memory before workgroup 0 reuses the tree's slots alone
+      if (!grid_barrier(a, gen, &s_fail, b, G_all)) {
+        if (tid == 0) __hip_atomic_store(&a.hdr->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+      }
+    }
+  }
+  // the others may be waiting for a hand-off: the call has ended
+  if (TIERED && b == 0 && tier0 > 0 && n <= tier0) {
+    const LoopState st = {n, round, iter, n_sol, (int)rounds_done, status, c_best, gen, it_done, 1};
+    publish_handoff(a, st);
   }
 
   if (b == 0 && tid == 0) {
@@ -780,7 +942,7 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
 __device__ __forceinline__ Smem make_smem(float* obs, float* tile, float* targets,
                                           unsigned long long* keys, int* cnt, int* off, int* wave, float* val,
                                           unsigned long long* goal, int* fail, int* misc,
-                                          Books* books) {
+                                          Books* books, LoopState* state) {
   Smem m;
   m.obs = obs;
   m.tile = tile;
@@ -794,6 +956,7 @@ __device__ __forceinline__ Smem make_smem(float* obs, float* tile, float* target
   m.fail = fail;
   m.misc = misc;
   m.books = books;
+  m.state = state;
   return m;
 }
 
@@ -812,11 +975,12 @@ __global__ __launch_bounds__(NT) void k_plan(KArgs a) {
   __shared__ int s_fail;
   __shared__ int s_misc[2];
   __shared__ Books s_books;
+  __shared__ LoopState s_state;
   const Smem sm = make_smem(s_obs, s_tile, s_targets, s_keys, s_cnt, s_off, s_wave, s_val,
-                            &s_goal, &s_fail, s_misc, &s_books);
+                            &s_goal, &s_fail, s_misc, &s_books, &s_state);
   // (above 6 state dimensions the plan keeps the plain scan: the node-slice
   // form costs the quadrotor's rollout code more than it saves)
-  plan_loop<SYS, QT, (Sys<SYS>::D <= 6)>(a, blockIdx.x, gridDim.x, sm);
+  plan_loop<SYS, QT, (Sys<SYS>::D <= 6), true>(a, blockIdx.x, gridDim.x, sm);
 }
 
 // Many queries in one launch: each workgroup takes the next query from a
@@ -843,8 +1007,9 @@ __global__ __launch_bounds__(NT) void k_batch(const KArgs* __restrict__ qs,
   __shared__ int s_misc[2];
   __shared__ int s_ticket;
   __shared__ Books s_books;
+  __shared__ LoopState s_state;
   const Smem sm = make_smem(s_obs, s_tile, s_targets, s_keys, s_cnt, s_off, s_wave, s_val,
-                            &s_goal, &s_fail, s_misc, &s_books);
+                            &s_goal, &s_fail, s_misc, &s_books, &s_state);
   while (true) {
     __syncthreads();  // everyone has read the previous s_ticket
     if (threadIdx.x == 0) {
@@ -857,15 +1022,15 @@ __global__ __launch_bounds__(NT) void k_batch(const KArgs* __restrict__ qs,
     const KArgs& a = qs[ticket >> 5];
     const int member = ticket & 31, team = a.P.G;
     switch (a.P.system) {
-      case PAKR_DI2: plan_loop<PAKR_DI2, 1, true>(a, member, team, sm); break;
-      case PAKR_DI3: plan_loop<PAKR_DI3, 1, true>(a, member, team, sm); break;
-      case PAKR_CAR: plan_loop<PAKR_CAR, 1, true>(a, member, team, sm); break;
-      case PAKR_DUBINS: plan_loop<PAKR_DUBINS, 1, true>(a, member, team, sm); break;
-      case PAKR_UNI1: plan_loop<PAKR_UNI1, 1, true>(a, member, team, sm); break;
-      case PAKR_UNI2: plan_loop<PAKR_UNI2, 1, true>(a, member, team, sm); break;
-      case PAKR_ACROBOT: plan_loop<PAKR_ACROBOT, 1, true>(a, member, team, sm); break;
-      case PAKR_CARTPOLE: plan_loop<PAKR_CARTPOLE, 1, true>(a, member, team, sm); break;
-      default: plan_loop<PAKR_QUAD, 1, true>(a, member, team, sm); break;
+      case PAKR_DI2: plan_loop<PAKR_DI2, 1, true, false>(a, member, team, sm); break;
+      case PAKR_DI3: plan_loop<PAKR_DI3, 1, true, false>(a, member, team, sm); break;
+      case PAKR_CAR: plan_loop<PAKR_CAR, 1, true, false>(a, member, team, sm); break;
+      case PAKR_DUBINS: plan_loop<PAKR_DUBINS, 1, true, false>(a, member, team, sm); break;
+      case PAKR_UNI1: plan_loop<PAKR_UNI1, 1, true, false>(a, member, team, sm); break;
+      case PAKR_UNI2: plan_loop<PAKR_UNI2, 1, true, false>(a, member, team, sm); break;
+      case PAKR_ACROBOT: plan_loop<PAKR_ACROBOT, 1, true, false>(a, member, team, sm); break;
+      case PAKR_CARTPOLE: plan_loop<PAKR_CARTPOLE, 1, true, false>(a, member, team, sm); break;
+      default: plan_loop<PAKR_QUAD, 1, true, false>(a, member, team, sm); break;
     }
   }
 }

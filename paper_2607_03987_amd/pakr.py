@@ -79,7 +79,8 @@ class Params(C.Structure):
                 ("h_speed", C.c_float), ("cost_bound", C.c_double), ("seed", C.c_uint64),
                 ("query_id", C.c_uint32), ("max_iters_per_round", C.c_int), ("grid", C.c_int),
                 ("max_path_edges", C.c_int), ("lanes_per_candidate", C.c_int),
-                ("workgroups_per_cu", C.c_int)]
+                ("workgroups_per_cu", C.c_int), ("spec_tiles", C.c_int),
+                ("tier0_nodes", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -223,7 +224,7 @@ class CQuery:
     """The C structs of one Problem (holds the host arrays alive)."""
 
     def __init__(self, prob: W.Problem, grid: int = 0, max_path_edges: int = 0, lanes: int = 0,
-                 wg_per_cu: int = 0):
+                 wg_per_cu: int = 0, spec: int = 0, tier0: int = 0):
         self.prob = prob
         s = System()
         s.id, s.d, s.m = prob.system, prob.d, prob.m
@@ -263,6 +264,8 @@ class CQuery:
         p.grid, p.max_path_edges = int(grid), int(max_path_edges)
         p.lanes_per_candidate = int(lanes)
         p.workgroups_per_cu = int(wg_per_cu)
+        p.spec_tiles = int(spec)
+        p.tier0_nodes = int(tier0)
         self.params = p
 
 
@@ -293,7 +296,7 @@ class Plan:
     """
 
     def __init__(self, prob: W.Problem, grid: int = 0, max_path_edges: int = 0, device=None,
-                 lanes: int = 0, wg_per_cu: int = 0):
+                 lanes: int = 0, wg_per_cu: int = 0, spec: int = 0, tier0: int = 0):
         import torch
 
         if not torch.cuda.is_available():
@@ -301,7 +304,7 @@ class Plan:
         self.torch = torch
         self.prob = prob
         self.q = CQuery(prob, grid=grid, max_path_edges=max_path_edges, lanes=lanes,
-                        wg_per_cu=wg_per_cu)
+                        wg_per_cu=wg_per_cu, spec=spec, tier0=tier0)
         self.device = torch.device(device or "cuda")
         nbytes = workspace_size(self.q)
         if nbytes == 0:
@@ -439,12 +442,13 @@ def _bcheck(rc: int, handle=None):
 class CBatch:
     """The C arrays of a list of Problems (holds the host arrays alive)."""
 
-    def __init__(self, probs, lanes=0, teams=0):
+    def __init__(self, probs, lanes=0, teams=0, spec=0, tier0=0):
         self.probs = list(probs)
         n = self.n = len(self.probs)
-        teams = [int(teams)] * n if isinstance(teams, int) else [int(t) for t in teams]
-        lanes = [int(lanes)] * n if isinstance(lanes, int) else [int(v) for v in lanes]
-        self.qs = [CQuery(p, lanes=v, grid=t) for p, v, t in zip(self.probs, lanes, teams)]
+        per = lambda v: [int(v)] * n if isinstance(v, int) else [int(x) for x in v]
+        teams, lanes, spec, tier0 = per(teams), per(lanes), per(spec), per(tier0)
+        self.qs = [CQuery(p, lanes=v, grid=t, spec=s, tier0=z)
+                   for p, v, t, s, z in zip(self.probs, lanes, teams, spec, tier0)]
         self.sys = (System * n)(*[q.system for q in self.qs])
         self.sc = (Scene * n)(*[q.scene for q in self.qs])
         self.goal = (Goal * n)(*[q.goal for q in self.qs])
@@ -474,13 +478,13 @@ class BatchPlan:
     the estimated work.
     """
 
-    def __init__(self, probs, lanes=0, device=None, teams=0):
+    def __init__(self, probs, lanes=0, device=None, teams=0, spec=0, tier0=0):
         import torch
 
         if not torch.cuda.is_available():
             raise RuntimeError("libpakr needs a ROCm GPU; none is visible")
         self.torch = torch
-        self.cb = CBatch(probs, lanes=lanes, teams=teams)
+        self.cb = CBatch(probs, lanes=lanes, teams=teams, spec=spec, tier0=tier0)
         self.probs = self.cb.probs
         nbytes = batch_workspace_size(self.cb)
         if nbytes == 0:

@@ -9,13 +9,18 @@ solved trials, the median time to the first solution, the iterations it took
 and the tree size when it was found.
 
 Run: python -m paper_2607_03987_amd.sweep [--trials N] [--limit-ms MS] [--out PATH]
-(needs a GPU).  Prints one JSON object and writes it to --out if given.
+[--md PATH] (needs a GPU).  Prints one JSON object and writes it to --out if
+given; --md writes the table in the paper's layout with the command and the
+SHA-256 of the kernel sources it ran.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
+import os
 import statistics
+import sys
 import time
 
 from . import pakr, workloads as W
@@ -43,6 +48,43 @@ def run_cell(B: int, A: int, trials: int, limit_ms: float, seed0: int = 0) -> di
             "time_ms": med(t_first), "iters": med(iters), "nodes": med(nodes)}
 
 
+_ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+KERNEL_SOURCES = ["paper_2607_03987_amd/csrc/pakr.hip", "paper_2607_03987_amd/csrc/pakr_device.hpp",
+                  "paper_2607_03987_amd/csrc/pakr_kernels.hpp", "include/pakr.h"]
+
+
+def source_sha256() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(_ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def markdown(out: dict, command: str) -> str:
+    """The study as a table shaped like the paper's (rows: B and metric, columns: A)."""
+    cells = {(c["B"], c["A"]): c for c in out["cells"]}
+    As = sorted({a for _, a in cells})
+    Bs = sorted({b for b, _ in cells})
+    fmt = lambda v, f: "-" if v is None else f.format(v)
+    lines = [f"# Batch size x branching factor on the quadrotor ({out['trials_per_cell']} trials "
+             f"per cell)", "",
+             out["workload"] + ".", "",
+             f"Command: `{command}`", "",
+             f"Device: {out['device']}; {out['seconds']} s; kernel sources sha256 "
+             f"{out.get('source_sha256', '?')}.", "",
+             "Medians over the solved trials of each cell (time to the first solution, the "
+             "iterations it took, the tree size then).", "",
+             "| B | metric | " + " | ".join(f"A = {a}" for a in As) + " |",
+             "|---|---|" + "---|" * len(As)]
+    for B in Bs:
+        for key, name, f in (("success_pct", "success %", "{:.0f}"), ("time_ms", "time ms", "{:.1f}"),
+                             ("iters", "iters", "{:.0f}"), ("nodes", "nodes", "{:.0f}")):
+            row = [fmt(cells[(B, a)][key], f) if (B, a) in cells else "-" for a in As]
+            lines.append(f"| {B} | {name} | " + " | ".join(row) + " |")
+    return "\n".join(lines) + "\n"
+
+
 def main():
     import torch
 
@@ -50,6 +92,7 @@ def main():
     ap.add_argument("--trials", type=int, default=20)
     ap.add_argument("--limit-ms", type=float, default=1000.0)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--md", default=None)
     args = ap.parse_args()
     if not torch.cuda.is_available():
         raise SystemExit("the sweep needs a GPU")
@@ -66,10 +109,13 @@ def main():
                        "(first solution) per trial",
            "trials_per_cell": args.trials, "limit_ms": args.limit_ms,
            "device": torch.cuda.get_device_name(0), "seconds": round(time.time() - t0, 1),
-           "cells": cells}
+           "source_sha256": source_sha256(), "cells": cells}
     if args.out:
         with open(args.out, "w") as f:
             json.dump(out, f, indent=1)
+    if args.md:
+        with open(args.md, "w") as f:
+            f.write(markdown(out, "python -m paper_2607_03987_amd.sweep " + " ".join(sys.argv[1:])))
     print(json.dumps(out), flush=True)
 
 

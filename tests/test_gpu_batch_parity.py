@@ -77,9 +77,10 @@ def test_batch_kernel_step_parity_against_reference():
 
 def test_batch_expand_equals_replan_iterations():
     """pakr_batch_expand(n) and pakr_batch_replan(max_iters = n) run the same
-    iterations, and expanding in pieces equals one call."""
+    iterations, expanding in pieces equals one call, and the tiles that idle
+    team members scan ahead (none or the automatic amount) change nothing."""
     probs = [p.replace(qid=q) for q, p in enumerate(mixed_queries()[:4])]
-    a = pakr.BatchPlan(probs, lanes=LANES[:4], teams=TEAMS[:4])
+    a = pakr.BatchPlan(probs, lanes=LANES[:4], teams=TEAMS[:4], spec=-1)
     b = pakr.BatchPlan(probs, lanes=LANES[:4], teams=TEAMS[:4])
     a.expand(3)
     a.expand(4)
@@ -92,3 +93,20 @@ def test_batch_expand_equals_replan_iterations():
             np.testing.assert_array_equal(x, y)
     a.close()
     b.close()
+
+
+def test_batch_launch_of_many_iterations_against_reference():
+    """A batch launch of many iterations (team members without a rollout chunk
+    scan ahead), each query's records compared with its own reference run."""
+    probs = [p.replace(qid=q, max_iters_per_round=12) for q, p in enumerate(mixed_queries())]
+    bp = pakr.BatchPlan(probs, lanes=LANES, teams=TEAMS)
+    orcs = [oracle.OraclePlan(p) for p in probs]
+    n_iters = 16
+    traces = bp.expand(n_iters, trace=True)
+    for q, (p, orc) in enumerate(zip(probs, orcs)):
+        print(f"query {q} {p.name}: {n_iters} iterations in one launch", flush=True)
+        for i, tr in enumerate(traces[q]):
+            rep = orc.iterate(steer=dict(parents=tr["parents"], flags=tr["flags"],
+                                         goal_j=tr["goal_j"]))
+            compare_iteration(p, tr, rep, ctx=f"batch launch query {q} ({p.name}) iter {i}")
+    bp.close()

@@ -147,6 +147,88 @@ def test_free_running_against_reference():
         assert rel_err([s["cost"] for s in sg], [s["cost"] for s in so]).max() <= 1e-4
 
 
+@pytest.mark.parametrize("cfg,kw,iters,tier0", [
+    ("c1", dict(seed=7, max_iters_per_round=45), 90, 0),
+    ("c1", dict(seed=7, max_iters_per_round=45), 90, 4096),
+    ("c1", dict(seed=7, max_iters_per_round=45), 90, -1),
+    ("c2", dict(seed=2, B=1024, A=8, n_cap=60000, max_iters_per_round=25), 40, 0),
+])
+def test_one_launch_of_many_iterations_against_reference(cfg, kw, iters, tier0):
+    """All iterations in one launch: workgroups without a rollout chunk scan
+    ahead for the next iteration and phase 1 skips what they covered, and
+    (c1) workgroup 0 runs the iterations alone while the tree is in the first
+    tier, handing over to the grid and back at every round; every
+    iteration's record is compared with the reference's own run."""
+    prob = W.CONFIGS[cfg](**kw)
+    print(f"case {prob.name} one launch of {iters} iterations, tier0 {tier0}", flush=True)
+    plan = pakr.Plan(prob, tier0=tier0)
+    orc = oracle.OraclePlan(prob)
+    traces = plan.expand(iters, trace=True)
+    rounds = set()
+    sizes = []
+    for i, tr in enumerate(traces):
+        rep = orc.iterate(steer=dict(parents=tr["parents"], flags=tr["flags"], goal_j=tr["goal_j"]))
+        compare_iteration(prob, tr, rep, ctx=f"{prob.name} launch iter {i}")
+        rounds.add(tr["round"])
+        sizes.append(tr["n0"])
+    assert len(rounds) >= 2, "the run should cross a round end"
+    if tier0 > 0:
+        # both tiers, in more than one round
+        assert min(sizes) <= tier0 < max(sizes)
+    plan.close()
+
+
+@pytest.mark.parametrize("cfg,kw,tiers", [
+    ("c1", dict(max_iters_per_round=80), (-1, 256, 1024, 4096, 0, 1 << 20)),
+    # a first tier whose rollout takes several passes of workgroup 0
+    ("c2", dict(B=1024, A=8, n_cap=60000, max_iters_per_round=40), (-1, 4096, 0)),
+])
+def test_tiers_do_not_change_results(cfg, kw, tiers):
+    """Where the first tier ends (never, 4^4 .. 4^6 nodes, auto, always)
+    changes no result."""
+    prob = W.CONFIGS[cfg](**kw)
+    res = []
+    for t in tiers:
+        p = pakr.Plan(prob, tier0=t)
+        p.replan(max_rounds=3)
+        st = p.status()
+        res.append((st["total_iters"], st["insertions"], st["nn_pairs"],
+                    [(x["round"], x["iter"], x["node"], x["cost"]) for x in p.solutions()],
+                    p.copy_tree()))
+        print(f"{prob.name} tier0 {t}: {st['total_iters']} iterations, {len(res[-1][3])} "
+              f"solutions", flush=True)
+        p.close()
+    for r in res[1:]:
+        assert r[:4] == res[0][:4]
+        for x, y in zip(r[4], res[0][4]):
+            np.testing.assert_array_equal(x, y)
+
+
+@pytest.mark.parametrize("cfg,kw", [
+    ("c1", dict(max_iters_per_round=80)),
+    ("c2", dict(B=1024, A=8, n_cap=60000, max_iters_per_round=40)),
+    ("c4", dict(B=512, A=16, n_cap=60000, max_iters_per_round=30)),
+])
+def test_scan_ahead_does_not_change_results(cfg, kw):
+    """The tiles scanned ahead by idle workgroups (none, some, all) change no result."""
+    prob = W.CONFIGS[cfg](**kw)
+    res = []
+    for spec in (-1, 1, 3, 0, 1024):
+        p = pakr.Plan(prob, spec=spec)
+        p.replan(max_rounds=3)
+        st = p.status()
+        res.append((st["total_iters"], st["insertions"], st["nn_pairs"],
+                    [(x["round"], x["iter"], x["node"], x["cost"]) for x in p.solutions()],
+                    p.copy_tree()))
+        print(f"{prob.name} spec {spec}: {st['total_iters']} iterations, "
+              f"{len(res[-1][3])} solutions", flush=True)
+        p.close()
+    for r in res[1:]:
+        assert r[:4] == res[0][:4]
+        for x, y in zip(r[4], res[0][4]):
+            np.testing.assert_array_equal(x, y)
+
+
 def test_extracted_path_is_feasible():
     prob = W.config_c1(max_iters_per_round=80)
     plan = pakr.Plan(prob)
@@ -170,20 +252,24 @@ def test_extracted_path_is_feasible():
     assert all(b["cost"] < a["cost"] for a, b in zip(sols, sols[1:]))
 
 
-@pytest.mark.parametrize("grid", [0, 3, 1])
-def test_budget_stop_ends_every_workgroup_at_one_iteration(grid):
+@pytest.mark.parametrize("cfg,grid,tier0", [("c2", 0, 0), ("c2", 3, 0), ("c2", 1, 0),
+                                            ("c1", 0, 1 << 20), ("c1", 0, 1024)])
+def test_budget_stop_ends_every_workgroup_at_one_iteration(cfg, grid, tier0):
     """Workgroup 0 takes the budget decision and every workgroup leaves at the
-    same iteration: the tree then equals that of a call capped at the same
-    number of iterations, and planning resumes from it."""
-    prob = W.config_c2(B=512, A=8, n_cap=200000)
-    print(f"case c2 budget 15 ms grid {grid}", flush=True)
-    a = pakr.Plan(prob, grid=grid)
+    same iteration -- also when it runs the first tier alone while the others
+    wait (c1: always, or in the first tier of each round): the tree then
+    equals that of a call capped at the same number of iterations, and
+    planning resumes from it."""
+    prob = (W.config_c2(B=512, A=8, n_cap=200000) if cfg == "c2"
+            else W.config_c1(max_iters_per_round=60))
+    print(f"case {cfg} budget 15 ms grid {grid} tier0 {tier0}", flush=True)
+    a = pakr.Plan(prob, grid=grid, tier0=tier0)
     a.replan(budget_ms=15.0)
     st = a.status()
     assert st["status"] & pakr.S_BUDGET_EXPIRED, st["status"]
     assert st["call_iters"] > 0
     assert 15.0 <= st["call_ms"] <= 15.0 + 10.0, st["call_ms"]
-    b = pakr.Plan(prob, grid=grid)
+    b = pakr.Plan(prob, grid=grid, tier0=tier0)
     b.replan(max_iters=st["call_iters"])
     sb = b.status()
     assert sb["status"] & pakr.S_ITERS_DONE and not sb["status"] & pakr.S_BUDGET_EXPIRED
