@@ -60,6 +60,45 @@ def compare_iteration(prob, tr, rep, ctx=""):
                 max_state_err=float(rel_err(tr["xnew"][ov], rep.xnew[ov]).max()) if ov.any() else 0.0)
 
 
+def replay_records(prob, traces, orc, ctx=""):
+    """Replay the records of a launch of many iterations in the reference.
+
+    Before each iteration the reference is re-seeded with the GPU's float32
+    tree as it stood then, rebuilt from the launch's own records (the root,
+    then every earlier record's inserted candidates at their slots), exactly
+    as step parity re-seeds it from a read-back of the tree.  A rollout is
+    thus always compared from the same parent state: along a path of many
+    edges the float32 and FP64 trees drift apart by the dynamics' own
+    amplification of rounding error (chaotic systems such as the acrobot
+    grow it past 1e-4 within a few edges), which says nothing about the
+    kernel.
+    """
+    d, m, A = prob.d, prob.m, prob.A
+    cap = prob.n_cap
+    S = np.zeros((cap, d), np.float32)
+    U = np.zeros((cap, m), np.float32)
+    Pa = np.full(cap, -1, np.int32)
+    C = np.zeros(cap, np.float32)
+    S[0] = np.asarray(prob.x_init, np.float32)
+    stats = []
+    for i, tr in enumerate(traces):
+        n0 = tr["n0"]
+        c = tr["c_best_before"]
+        orc.load_tree(S[:n0], U[:n0], Pa[:n0], C[:n0], tr["round"], tr["iter"],
+                      c if np.isfinite(c) else np.inf)
+        rep = orc.iterate(steer=dict(parents=tr["parents"], flags=tr["flags"],
+                                     goal_j=tr["goal_j"]))
+        stats.append(compare_iteration(prob, tr, rep, ctx=f"{ctx} iter {i} (round {tr['round']})"))
+        js = np.nonzero(tr["slots"] >= 0)[0]
+        sl = tr["slots"][js]
+        assert sl.size == 0 or (sl.min() >= n0 and sl.max() < cap), (ctx, i)
+        S[sl] = tr["xnew"][js]
+        U[sl] = tr["controls"][js]
+        Pa[sl] = tr["parents"][js // A]
+        C[sl] = tr["cnew"][js]
+    return stats
+
+
 def step_parity(prob, n_iters, grid=0, log=None, lanes=0):
     """Run n_iters GPU iterations one at a time; replay each in the reference."""
     plan = pakr.Plan(prob, grid=grid, lanes=lanes)
