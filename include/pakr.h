@@ -432,6 +432,22 @@ size_t pakr_refine_workspace_size(const pakr_refiner* r, int n, int M);
 int pakr_refine_paths(pakr_refiner* r, int n, int M, const float* d_x0, float* d_U, int steps,
                       float lr, void* d_ws, size_t ws_bytes, float* d_J_before, float* d_J_after);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * refinement as pakr_refine_paths, with its work buffers (checkpoints, Adam
+ * moments, trial controls, per-path J and step sizes) in a library-owned
+ * static device array of PAKR_REFINE_STATIC_BYTES per GPU instead of a
+ * caller workspace.  The array's address on a GPU is looked up once, when
+ * the first refiner is created with that GPU current; the call itself
+ * allocates nothing.  Sizes whose pakr_refine_workspace_size exceeds the
+ * array fail with PAKR_E_WORKSPACE_TOO_SMALL.  Every call on one GPU shares
+ * its array, so calls that may overlap on a GPU (different streams, or
+ * refiners on different streams) race: order them.  Results equal
+ * pakr_refine_paths' bit for bit.  Async on the refiner's stream. */
+#define PAKR_REFINE_STATIC_BYTES (16u << 20)
+int pakr_refine_paths_static(pakr_refiner* r, int n, int M, const float* d_x0, float* d_U,
+                             int steps, float lr, float* d_J_before, float* d_J_after);
+
 /* The planner's acceptance test of each path: ok bit 0 = every sub-step
  * state valid (workspace, limits, obstacles), bit 1 = final position in the
  * goal ball; cost = the path's cost under cost_kind.  Async. */

@@ -1348,6 +1348,7 @@ void pakr_batch_destroy(pakr_batch* bt) {
 struct pakr_refiner {
   DevProblem P;
   RefineParams R;
+  int device = 0;  // current device when the refiner was created
   hipStream_t stream = nullptr;
   float* obs = nullptr;
   size_t shmem = 0;
@@ -1356,6 +1357,31 @@ struct pakr_refiner {
 
 
 namespace {
+
+// Work buffers of pakr_refine_paths_static: one copy of this array per GPU,
+// held until the process ends.  Its name is a host-side stand-in: host code
+// uses the device address looked up per device (refine_scratch_on).
+constexpr int MAX_DEVICES = 64;
+__device__ __align__(256) unsigned char scratch[PAKR_REFINE_STATIC_BYTES];
+// (trivially destructible: nothing runs at process exit)
+std::atomic<void*> g_scratch_ptr[MAX_DEVICES];
+
+// Device address of `scratch` on `dev`, which must be the current device;
+// looked up on the first call per device (idempotent, so concurrent first
+// calls store the same value).  nullptr with *err set if the lookup fails.
+void* refine_scratch_on(int dev, hipError_t* err) {
+  *err = hipSuccess;
+  if (dev < 0 || dev >= MAX_DEVICES) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  void* p = g_scratch_ptr[dev].load(std::memory_order_acquire);
+  if (p != nullptr) return p;
+  *err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (*err != hipSuccess) return nullptr;
+  g_scratch_ptr[dev].store(p, std::memory_order_release);
+  return p;
+}
 
 int rfail(pakr_refiner* r, int code, const std::string& msg) {
   if (r) r->err = msg;
@@ -1562,6 +1588,16 @@ int pakr_refiner_init(const pakr_system* sys, const pakr_scene* scene, const pak
   pakr_refiner* r = new (std::nothrow) pakr_refiner();
   if (!r) return rfail(nullptr, PAKR_E_INVALID_ARG, "out of host memory");
   r->stream = static_cast<hipStream_t>(stream);
+  hipError_t e = hipGetDevice(&r->device);
+  // set-up of pakr_refine_paths_static: the static work array's address on
+  // this device, looked up now so that the entry point itself does nothing
+  // but launch kernels
+  if (e == hipSuccess) (void)refine_scratch_on(r->device, &e);
+  if (e != hipSuccess) {
+    int rc = rfail(nullptr, PAKR_E_HIP, std::string("refiner set-up: ") + hipGetErrorString(e));
+    delete r;
+    return rc;
+  }
   // the planner's record of the query; B, A, n_cap do not matter here
   pakr_params prm = *params;
   prm.B = 1;
@@ -1571,7 +1607,7 @@ int pakr_refiner_init(const pakr_system* sys, const pakr_scene* scene, const pak
   r->R = to_device(*refine);
   const std::vector<float> obs = pack_obstacles(*scene);
   r->shmem = sizeof(float) * std::max<size_t>(obs.size(), 1);
-  hipError_t e = hipMalloc(&r->obs, r->shmem);
+  e = hipMalloc(&r->obs, r->shmem);
   if (e == hipSuccess && !obs.empty())
     e = hipMemcpyAsync(r->obs, obs.data(), sizeof(float) * obs.size(), hipMemcpyHostToDevice,
                        r->stream);
@@ -1730,6 +1766,24 @@ int pakr_refine_paths(pakr_refiner* r, int n, int M, const float* d_x0, float* d
   if ((reinterpret_cast<uintptr_t>(d_ws) & 255) != 0)
     return rfail(r, PAKR_E_INVALID_ARG, "workspace must be 256-byte aligned");
   return refine_paths_at(r, n, M, d_x0, d_U, steps, lr, static_cast<char*>(d_ws), L, d_J_before,
+                         d_J_after);
+}
+
+int pakr_refine_paths_static(pakr_refiner* r, int n, int M, const float* d_x0, float* d_U,
+                             int steps, float lr, float* d_J_before, float* d_J_after) {
+  if (!r) return PAKR_E_INVALID_ARG;
+  int rc = refine_args_ok(r, n, M, d_x0, d_U, steps, lr);
+  if (rc != PAKR_OK) return rc;
+  const RefineLayout L = refine_layout(r, n, M);
+  if (L.total > (size_t)PAKR_REFINE_STATIC_BYTES)
+    return rfail(r, PAKR_E_WORKSPACE_TOO_SMALL,
+                 "refinement buffers of " + std::to_string(L.total) +
+                     " bytes exceed the static array of " +
+                     std::to_string((size_t)PAKR_REFINE_STATIC_BYTES) + " bytes");
+  // looked up when the refiner was created (this call then allocates nothing)
+  void* base = g_scratch_ptr[r->device].load(std::memory_order_acquire);
+  if (base == nullptr) return rfail(r, PAKR_E_HIP, "static refinement array not set up");
+  return refine_paths_at(r, n, M, d_x0, d_U, steps, lr, static_cast<char*>(base), L, d_J_before,
                          d_J_after);
 }
 

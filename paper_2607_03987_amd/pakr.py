@@ -44,7 +44,7 @@ EXPORTED = ["pakr_workspace_size", "pakr_plan_init", "pakr_plan_destroy", "pakr_
             "pakr_batch_last_error", "pakr_batch_destroy",
             "pakr_refiner_init", "pakr_refiner_set_params", "pakr_rollout_ckpt_bytes",
             "pakr_rollout_fwd", "pakr_rollout_bwd", "pakr_refine_step", "pakr_check_path",
-            "pakr_refine_workspace_size", "pakr_refine_paths",
+            "pakr_refine_workspace_size", "pakr_refine_paths", "pakr_refine_paths_static",
             "pakr_refiner_last_error", "pakr_refiner_destroy"]
 
 
@@ -206,6 +206,9 @@ def load():
         L.pakr_refine_paths.argtypes = [vp, C.c_int, C.c_int, vp, vp, C.c_int, C.c_float, vp, sz,
                                         vp, vp]
         L.pakr_refine_paths.restype = C.c_int
+        L.pakr_refine_paths_static.argtypes = [vp, C.c_int, C.c_int, vp, vp, C.c_int, C.c_float,
+                                               vp, vp]
+        L.pakr_refine_paths_static.restype = C.c_int
         L.pakr_check_path.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, vp]
         L.pakr_check_path.restype = C.c_int
         L.pakr_refiner_last_error.argtypes = [vp]

@@ -205,3 +205,31 @@ def refine_path(refiner: Refiner, x0, U, steps: int | None = None, lr: float | N
     U_out = torch.where(accepted[:, None, None], Uw, U0)
     return dict(U_refined=Uw, U_out=U_out, J_before=J0, J_after=J1, ok=ok, cost=cost,
                 accepted=accepted, workspace=ws)
+
+
+REFINE_STATIC_BYTES = 16 << 20  # PAKR_REFINE_STATIC_BYTES
+
+
+def refine_controls_static(refiner: Refiner, x0, U, steps: int | None = None,
+                           lr: float | None = None):
+    """pakr_refine_paths_static: the refinement loop of `refine_path` with its
+    work buffers in the library's static per-GPU array (no workspace is
+    allocated by the call).  U [n][M][m] is refined in place; returns
+    (J_before, J_after).  Calls on one GPU share the array: do not overlap
+    them."""
+    torch = refiner.torch
+    s = refiner.settings
+    steps = s.steps if steps is None else int(steps)
+    lr = s.lr if lr is None else float(lr)
+    n, M = int(U.shape[0]), int(U.shape[1])
+    dev = refiner.device.index if refiner.device.index is not None else torch.cuda.current_device()
+    if not (U.is_cuda and U.get_device() == dev and U.is_contiguous() and
+            U.dtype == torch.float32):
+        raise ValueError("U must be a contiguous float32 tensor on the refiner's device")
+    x0 = refiner._f32(x0, (n, refiner.d))
+    J0 = torch.empty(n, dtype=torch.float32, device=refiner.device)
+    J1 = torch.empty_like(J0)
+    rc = pakr.load().pakr_refine_paths_static(refiner.h, n, M, x0.data_ptr(), U.data_ptr(),
+                                              steps, lr, J0.data_ptr(), J1.data_ptr())
+    _rcheck(rc, refiner.h)
+    return J0, J1
