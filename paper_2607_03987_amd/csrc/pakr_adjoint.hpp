@@ -594,7 +594,7 @@ __global__ __launch_bounds__(WAVE) void k_check_path(TrajArgs a) {
         const float d = x[c] - xp[c];
         s2 += d * d;
       }
-      len += sqrtf(s2);
+      len += __builtin_amdgcn_sqrtf(s2);  // as the planner's rollout
       float pos[1][NP];
 #pragma unroll
       for (int c = 0; c < NP; ++c) pos[0][c] = x[c];

@@ -647,7 +647,7 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
                   const float e = x[c] - xp[c];
                   s2 += e * e;
                 }
-                len += sqrtf(s2);
+                len += __builtin_amdgcn_sqrtf(s2);  // v_sqrt_f32 (1 ulp)
               }
               lim_ok = lim_ok & limits_ok<SYS>(s_val, x);
             }
