@@ -37,6 +37,9 @@ def flops_per_expansion(prob):
     combination, four evaluations of f, the per-step validity arithmetic
     (speed norm 2P, boxes P each, spheres 3P each) and, for a path-length
     cost, 3P + 1.  Plus the edge cost, goal distance and heuristic once.
+    The double integrators' RK4 step is the closed-form map it equals
+    (p + h v + h^2/2 u, v + h u: three FMAs, 6 FLOP, per axis), so it is
+    credited 6P, not the stage arithmetic.
     """
     from paper_2607_03987_amd import workloads as W
     d, P = prob.d, prob.npos
@@ -44,7 +47,8 @@ def flops_per_expansion(prob):
               W.ACROBOT: 38, W.CARTPOLE: 6}[prob.system]
     nb, ns = prob.box_c.shape[0], prob.sph_r.shape[0]
     speed = 2 * P if float(prob.vnorm_max) > 0 else 0
-    step = 12 * d + 4 * f_eval + speed + P * nb + 3 * P * ns
+    rk4 = 6 * P if prob.system in (W.DI2, W.DI3) else 12 * d + 4 * f_eval
+    step = rk4 + speed + P * nb + 3 * P * ns
     if prob.cost_kind == W.COST_PATH_LENGTH:
         step += 3 * P + 1
     return prob.T * step + 3 * P + 6
@@ -86,6 +90,48 @@ def measured_traffic():
         return None
     return 1024.0 * (float(vals["fetch_kib_per_dispatch"]) * float(vals["fetch_factor"]) +
                      float(vals["write_kib_per_dispatch"]) * float(vals["write_factor"]))
+
+
+VALU_SUMMARY = os.path.join(ROOT, "profiles", "k_plan_valu_counters.md")
+
+
+def measured_valu(kernel: str):
+    """Executed FP32 work of one kernel from the committed rocprofv3 counter runs.
+
+    The summary holds, per kernel, lines `<kernel>.<field>: value` with
+    executed_tflops (64 x SQ_INSTS_VALU_FLOPS_FP32, which counts the FLOPs of
+    one wave instruction, over the dispatch time), valu_busy (SQ_ACTIVE_INST_VALU
+    quad-cycles over the SIMDs' quad-cycles), active_lanes (SQ_THREAD_CYCLES_VALU
+    / SQ_ACTIVE_INST_VALU, of 64) and flops_per_lane_inst; None once the kernel
+    sources no longer hash to the profiled ones.
+    """
+    import hashlib
+    try:
+        txt = open(VALU_SUMMARY).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in txt.splitlines():
+        if ":" not in line or " " in line.split(":")[0]:
+            continue
+        k, v = line.split(":", 1)
+        if v.split():
+            vals[k] = v.split()[0]
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if vals.get("source_sha256") != h.hexdigest():
+        return None
+    out = {}
+    for field in ("executed_tflops", "valu_busy", "active_lanes", "flops_per_lane_inst"):
+        v = vals.get(f"{kernel}.{field}")
+        if v is None:
+            return None
+        out[field] = float(v)
+    out["executed_frac"] = out["executed_tflops"] / FP32_VECTOR_PEAK_TFLOPS
+    out["source"] = "rocprofv3 --pmc counters, " + os.path.relpath(VALU_SUMMARY, ROOT)
+    return out
 
 
 def batched_vs_plain(torch, pakr, W, n_queries, rounds, iters_per_round, lanes=None,
@@ -156,7 +202,8 @@ def batched_vs_plain(torch, pakr, W, n_queries, rounds, iters_per_round, lanes=N
                                  "achieved": batch_flops / (batch_ms / 1e3) / 1e12,
                                  "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                                  "frac": batch_flops / (batch_ms / 1e3) / 1e12 /
-                                 FP32_VECTOR_PEAK_TFLOPS}},
+                                 FP32_VECTOR_PEAK_TFLOPS,
+                                 "executed": measured_valu("k_batch")}},
         "plain": {"queries_per_s": n_queries / (sum(p_ms) / 1e3), "total_ms": sum(p_ms),
                   "wall_ms": plain_wall * 1e3,
                   "p50_alone_ms": pct(p_ms, 50), "p99_alone_ms": pct(p_ms, 99),
@@ -321,7 +368,8 @@ def saturating_rollout_leg(torch, pakr, W, iters, B=65536, A=16):
            "grid": st["grid"], "step_ms": [round(v, 3) for v in st["step_ms"]],
            "roofline": {"bound": "alu", "kernel": "k_plan<QUAD>", "achieved": tf,
                         "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                        "frac": tf / FP32_VECTOR_PEAK_TFLOPS}}
+                        "frac": tf / FP32_VECTOR_PEAK_TFLOPS,
+                        "executed": measured_valu("k_plan_quad_b65536")}}
     pl.close()
     return out
 
@@ -485,9 +533,9 @@ def main():
     ap.add_argument("--c1-seeds", type=int, default=100)
     ap.add_argument("--c1-budget-ms", type=float, default=50.0)
     ap.add_argument("--c2-seeds", type=int, default=100)
-    ap.add_argument("--c3-seeds", type=int, default=20)
+    ap.add_argument("--c3-seeds", type=int, default=100)
     ap.add_argument("--c3-budget-ms", type=float, default=200.0)
-    ap.add_argument("--c4-seeds", type=int, default=10)
+    ap.add_argument("--c4-seeds", type=int, default=50)
     ap.add_argument("--c4-budget-ms", type=float, default=500.0)
     ap.add_argument("--saturating-iters", type=int, default=50)
     ap.add_argument("--refine-budget-ms", type=float, default=500.0)
@@ -616,6 +664,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
                      "traffic": measured_traffic(),
+                     "executed": measured_valu("k_plan_di3"),
                      "kernel": "k_plan<DI3> (persistent AO-x planner), one launch per query"},
         "cpu_baseline": None,
         "batched": None,

@@ -164,25 +164,38 @@ struct Trig {
   float s[3], c[3], t;
 };
 
+// The planner's sines and cosines come from the hardware v_sin_f32 /
+// v_cos_f32 (the angle scaled to revolutions; absolute error about 1e-6 at
+// these angles, a few 1e-6 m in an edge's end position against the FP64
+// reference, below the 1e-5 decision band and the 1e-4 state bar) rather
+// than the correctly rounded library sincos, whose range reduction makes the
+// rollout's serial chain several times longer on the trigonometric systems.
+__device__ __forceinline__ void hw_sincos(float a, float* s, float* c) {
+  *s = __sinf(a);
+  *c = __cosf(a);
+}
+
 template <int SYS>
 __device__ __forceinline__ Trig trig_of(const float* x) {
   Trig g;
   if constexpr (SYS == PAKR_CAR) {
-    sincosf(x[2], &g.s[0], &g.c[0]);
-    g.t = tanf(x[4]);
+    hw_sincos(x[2], &g.s[0], &g.c[0]);
+    float sp, cp;
+    hw_sincos(x[4], &sp, &cp);
+    g.t = sp * __builtin_amdgcn_rcpf(cp);  // tan of the steering angle (|phi| <= 0.6)
   } else if constexpr (SYS == PAKR_QUAD) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) sincosf(x[3 + k], &g.s[k], &g.c[k]);
+    for (int k = 0; k < 3; ++k) hw_sincos(x[3 + k], &g.s[k], &g.c[k]);
   } else if constexpr (SYS == PAKR_DUBINS) {
-    sincosf(x[3], &g.s[0], &g.c[0]);
-    sincosf(x[4], &g.s[1], &g.c[1]);
+    hw_sincos(x[3], &g.s[0], &g.c[0]);
+    hw_sincos(x[4], &g.s[1], &g.c[1]);
   } else if constexpr (SYS == PAKR_UNI1 || SYS == PAKR_UNI2) {
-    sincosf(x[2], &g.s[0], &g.c[0]);
+    hw_sincos(x[2], &g.s[0], &g.c[0]);
   } else if constexpr (SYS == PAKR_CARTPOLE) {
-    sincosf(x[1], &g.s[0], &g.c[0]);
+    hw_sincos(x[1], &g.s[0], &g.c[0]);
   } else if constexpr (SYS == PAKR_ACROBOT) {
-    sincosf(x[0], &g.s[0], &g.c[0]);
-    sincosf(x[1], &g.s[1], &g.c[1]);
+    hw_sincos(x[0], &g.s[0], &g.c[0]);
+    hw_sincos(x[1], &g.s[1], &g.c[1]);
     g.s[2] = g.s[0] * g.c[1] + g.c[0] * g.s[1];  // angle sum
     g.c[2] = g.c[0] * g.c[1] - g.s[0] * g.s[1];
   }
