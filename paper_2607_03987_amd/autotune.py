@@ -94,16 +94,21 @@ def tune_batch(torch, n_per_system=48, iters_per_round=50, log=print) -> dict:
     return {"batch": res}
 
 
-def tune_single(torch, budget_ms=100.0, log=print) -> dict:
+def tune_single(torch, budget_ms=200.0, seeds=(0, 1, 2, 3, 4, 5), log=print) -> dict:
     best = None
     for L in (2, 4, 8, 16):
         for k in (1, 2):
-            plan = pakr.Plan(W.config_c2(seed=0), lanes=L, wg_per_cu=k)
-            plan.replan(budget_ms=budget_ms)
-            st = plan.status()
-            rate = st["expansions"] / (st["call_ms"] / 1e3)
-            log(f"single c2 lanes {L} workgroups/CU {k}: {rate / 1e6:.1f} M expansions/s")
-            plan.close()
+            exp, ms = 0, 0.0
+            for sd in seeds:
+                plan = pakr.Plan(W.config_c2(seed=sd), lanes=L, wg_per_cu=k)
+                plan.replan(budget_ms=budget_ms)
+                st = plan.status()
+                exp += st["expansions"]
+                ms += st["call_ms"]
+                plan.close()
+            rate = exp / (ms / 1e3)
+            log(f"single c2 lanes {L} workgroups/CU {k}: {rate / 1e6:.1f} M expansions/s "
+                f"over seeds {list(seeds)}")
             if best is None or rate > best[0]:
                 best = (rate, L, k)
     return {"single": {"lanes": best[1], "workgroups_per_cu": best[2],

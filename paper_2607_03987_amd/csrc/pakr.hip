@@ -68,19 +68,19 @@ int sys_m(int id) {
   return -1;
 }
 
-// Estimated instructions of one evaluation of f beyond its linear part: the
-// transcendental functions dominate (three sincos and a reciprocal for the
-// quadrotor, a sincos and a tangent for the car, two sincos and a division
-// for the acrobot, one or two sincos for the others).
+// Estimated operations of one evaluation of f beyond its linear part: its
+// arithmetic plus ~4 for each hardware sine/cosine pair (three and a
+// reciprocal for the quadrotor, two and a reciprocal for the car, two and a
+// division for the acrobot, one or two for the others).
 double f_eval_of(int id) {
   switch (id) {
-    case PAKR_QUAD: return 204.0;
-    case PAKR_CAR: return 128.0;
-    case PAKR_DUBINS: return 120.0;
-    case PAKR_ACROBOT: return 140.0;
+    case PAKR_QUAD: return 96.0;
+    case PAKR_CAR: return 24.0;
+    case PAKR_DUBINS: return 24.0;
+    case PAKR_ACROBOT: return 56.0;
     case PAKR_UNI1:
     case PAKR_UNI2:
-    case PAKR_CARTPOLE: return 64.0;
+    case PAKR_CARTPOLE: return 16.0;
   }
   return 0.0;
 }
@@ -947,8 +947,8 @@ namespace {
 
 // Relative cost of one iteration of a query on one workgroup, for scheduling
 // only: a fixed part (barriers, scans, bookkeeping), the rollout of the B
-// candidates (an evaluation of f counted with its sincos/tan calls at ~40
-// operations each) and the NN scan of K targets over a tree taken as 2 % of
+// candidates (an evaluation of f counted with its hardware sine and cosine
+// at ~4 operations each) and the NN scan of K targets over a tree taken as 2 % of
 // what one round could insert.  Calibrated against measured iteration times
 // (quadrotor ~2.6 ms, 3D double integrator ~0.15 ms on one workgroup).
 double query_work(const DevProblem& Q) {
