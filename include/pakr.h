@@ -202,6 +202,14 @@ typedef struct pakr_stats {
                                       the second barrier, insertion + bookkeeping        */
   double clock_start_ms;           /* device clock (ms) when the last call started this query */
   double clock_end_ms;             /* ... and when it finished it                        */
+  /* Near ties since pakr_plan_init: valid candidates whose prune decision
+   * c + h < c_best had |c + h - c_best| <= 1e-5 * max(1, c_best), and whose
+   * goal test had | |pos - g| - r | <= 1e-5 -- decisions that float32 and an
+   * FP64 evaluation may take differently.  (Nearest-neighbour and obstacle-
+   * margin ties would need the second-best distance and every sub-step's
+   * signed margin; they are not counted here.) */
+  long long near_ties_prune;
+  long long near_ties_goal;
 } pakr_stats;
 
 typedef struct pakr_solution {

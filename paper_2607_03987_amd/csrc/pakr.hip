@@ -555,6 +555,8 @@ void fill_stats(const DevHeader& h, double tpm, int grid, pakr_stats* out) {
   out->insert_ms = out->step_ms[5];
   out->clock_start_ms = (double)h.t_start / tpm;
   out->clock_end_ms = (double)h.t_end / tpm;
+  out->near_ties_prune = (long long)h.near_prune;
+  out->near_ties_goal = (long long)h.near_goal;
 }
 
 // Shared read-back helpers (each syncs `stream`).

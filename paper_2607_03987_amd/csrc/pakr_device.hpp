@@ -16,6 +16,9 @@ constexpr int TILE = 64;         // tree nodes per NN tile (unit of ownership)
 template <int QT>
 constexpr int NN_KC = QT * NT < 1024 ? QT * NT : 1024;
 constexpr int WAVE = 64;
+// Decision margins at or below this (relative to max(1, bound) for the prune,
+// absolute for the goal radius) are counted as near ties.
+constexpr float NEAR_TIE = 1e-5f;
 constexpr int MAX_SOLUTIONS = 1024;
 constexpr int MAX_GR = 1024;     // rollout workgroups per iteration
 constexpr int VAL_FLOATS = 32;   // validity record held in LDS (see load_validity)
@@ -66,6 +69,9 @@ struct DevHeader {
   int ho_rounds, ho_status;
   uint32_t ho_gen;
   long long ticks[8];                        // per-step device time of the last call
+  // candidates whose prune or goal decision lay within the near-tie band
+  // (since initialisation; added by the rollout waves that saw one)
+  unsigned long long near_prune, near_goal;
 };
 
 struct DevSolution {

@@ -615,6 +615,7 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
       bool valid = false, prune_ok = false, in_goal = false;
       int parent = 0, k = 0, br = 0;
       bool hit = false;
+      float margin_p = INFINITY, margin_g = INFINITY;  // prune and goal decision margins
       if (active) {
         k = j / A;
         br = j - k * A;
@@ -659,14 +660,25 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
         hit = hit | !lim_ok;
         cost = c_par + (path_len ? len : P.edge_duration);
         const float dist = sqrtf(goal_dist2<SYS>(P, x));
-        prune_ok = (cost + heuristic<SYS>(P, dist)) < c_best;
+        const float ch = cost + heuristic<SYS>(P, dist);
+        prune_ok = ch < c_best;
         in_goal = dist <= P.goal_r;
+        if (!__builtin_isinf(c_best)) margin_p = fabsf(ch - c_best) / fmaxf(1.0f, c_best);
+        margin_g = fabsf(dist - P.goal_r);
       }
       int hi = hit ? 1 : 0;
       for (int o = 1; o < L; o <<= 1) hi |= __shfl_xor(hi, o);
       valid = active && hi == 0;
       const bool lead = lg == 0;
       const bool keep = lead && active && valid && prune_ok;
+      // near ties (decisions within 1e-5 of their threshold, where float32
+      // and FP64 evaluations may decide differently), counted per wave
+      const unsigned long long tie_p = __ballot(lead && valid && margin_p <= NEAR_TIE);
+      const unsigned long long tie_g = __ballot(lead && valid && margin_g <= NEAR_TIE);
+      if ((tid & (WAVE - 1)) == 0 && (tie_p | tie_g) != 0ull) {
+        if (tie_p) atomicAdd(&a.hdr->near_prune, (unsigned long long)__popcll(tie_p));
+        if (tie_g) atomicAdd(&a.hdr->near_goal, (unsigned long long)__popcll(tie_g));
+      }
       const unsigned long long mask = __ballot(keep);
       const int lane = tid & (WAVE - 1), wv = tid / WAVE;
       const int wrank = __popcll(mask & ((1ull << lane) - 1ull));

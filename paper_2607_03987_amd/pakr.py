@@ -92,7 +92,8 @@ class Stats(C.Structure):
                 ("call_rounds", C.c_int), ("call_solutions", C.c_int), ("reserved", C.c_int),
                 ("nn_ms", C.c_double), ("rollout_ms", C.c_double), ("insert_ms", C.c_double),
                 ("step_ms", C.c_double * 6), ("clock_start_ms", C.c_double),
-                ("clock_end_ms", C.c_double)]
+                ("clock_end_ms", C.c_double), ("near_ties_prune", C.c_longlong),
+                ("near_ties_goal", C.c_longlong)]
 
 
 class Solution(C.Structure):

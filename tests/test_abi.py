@@ -49,7 +49,7 @@ int main(void) {
   P(pakr_refine_params, delta); P(pakr_refine_params, u_ref); P(pakr_refine_params, u_scale);
   P(pakr_system, vnorm_max); P(pakr_scene, sph_r); P(pakr_params, cost_bound);
   P(pakr_params, seed); P(pakr_params, max_path_edges); P(pakr_params, lanes_per_candidate); P(pakr_params, workgroups_per_cu); P(pakr_params, spec_tiles); P(pakr_params, tier0_nodes); P(pakr_stats, c_best);
-  P(pakr_stats, call_iters); P(pakr_stats, insert_ms); P(pakr_stats, step_ms); P(pakr_stats, clock_end_ms); P(pakr_solution, t_ms);
+  P(pakr_stats, call_iters); P(pakr_stats, insert_ms); P(pakr_stats, step_ms); P(pakr_stats, clock_end_ms); P(pakr_stats, near_ties_goal); P(pakr_solution, t_ms);
   return 0;
 }
 """

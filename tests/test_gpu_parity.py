@@ -53,6 +53,48 @@ def test_step_parity_prune_rules(cfg, kw, iters):
     assert 0 < kept < valid, (kept, valid)
 
 
+def _goal_ties(prob, tr):
+    """Valid candidates of a record within 1e-5 of the goal radius (FP64 recount)."""
+    valid = (tr["flags"] & pakr.F_VALID) != 0
+    pos = tr["xnew"][:, :prob.npos].astype(np.float64)
+    dist = np.linalg.norm(pos - np.asarray(prob.goal_c, np.float64)[:prob.npos], axis=1)
+    return int((valid & (np.abs(dist - float(prob.goal_r)) <= 1e-5)).sum())
+
+
+def _prune_ties(tr):
+    """Valid candidates of a record within 1e-5 (relative) of the bound, h = 0."""
+    valid = (tr["flags"] & pakr.F_VALID) != 0
+    cb = tr["c_best_before"]
+    if not np.isfinite(cb):
+        return 0
+    m = np.abs(tr["cnew"].astype(np.float64) - cb) / max(1.0, cb)
+    return int((valid & (m <= 1e-5)).sum())
+
+
+def test_near_tie_counters():
+    """pakr_stats counts the candidates whose prune or goal decision lay within
+    the near-tie band.  With h = 0 and the initial bound 5e-6 above one edge's
+    duration, every valid child of the root is a prune near tie (cost = T dt,
+    margin 5e-6 relative) and every deeper candidate is a whole edge away from
+    the bound; both counts equal recounts from the iterations' records."""
+    edge = float(np.float32(20) * np.float32(0.05))
+    prob = W.config_c2(seed=3, B=512, A=8, n_cap=20000, h_kind=W.H_NONE, c0=edge + 5e-6)
+    plan = pakr.Plan(prob)
+    st0 = plan.status()
+    assert st0["near_ties_prune"] == 0 and st0["near_ties_goal"] == 0
+    tr = plan.expand(1, trace=True)[0]
+    valid = int(((tr["flags"] & pakr.F_VALID) != 0).sum())
+    st = plan.status()
+    assert valid > 0 and _prune_ties(tr) == valid   # the construction holds
+    assert st["near_ties_prune"] == valid, (st["near_ties_prune"], valid)
+    assert st["near_ties_goal"] == _goal_ties(prob, tr)
+    trs = plan.expand(3, trace=True)
+    st2 = plan.status()
+    assert st2["near_ties_prune"] == valid + sum(_prune_ties(t) for t in trs)
+    assert st2["near_ties_goal"] == st["near_ties_goal"] + sum(_goal_ties(prob, t) for t in trs)
+    plan.close()
+
+
 @pytest.mark.parametrize("kw", [
     dict(B=300, A=3, n_cap=5000),          # ragged: B not a multiple of 256, K = 100
     dict(B=8, A=8, n_cap=2000),            # K = 1
