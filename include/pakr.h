@@ -173,6 +173,15 @@ typedef struct pakr_params {
                                       (a power of 4 from the query's sizes), -1 = none.
                                       Single-query plans only: a batch's team always plans
                                       together                                            */
+  int tier1_nodes;                 /* second tier: while a round's tree has more than
+                                      tier0_nodes and at most this many nodes, only the first
+                                      tier1_grid workgroups run each iteration (their
+                                      barriers are cheaper; results do not depend on it);
+                                      0 = auto (a power of 4 from the query's sizes), -1 =
+                                      none.  Single-query plans only                      */
+  int tier1_grid;                  /* workgroups of the second tier, 0 = auto (at least
+                                      the rollout workgroups of one batch and 32), else
+                                      2..grid                                             */
 } pakr_params;
 
 typedef struct pakr_stats {

@@ -100,6 +100,9 @@ int lanes_for(const pakr_params& p, int n_obs, int grid_limit) {
   return L;
 }
 
+// (defined below make_problem's helpers)
+void tier1_for(const pakr_params& prm, DevProblem* Q);
+
 // Rollout threads per workgroup.  A candidate's rollout is one serial chain
 // per lane; when that chain is long (car, quadrotor: trigonometry in every
 // evaluation of f) half the workgroup takes candidates, so each SIMD runs one
@@ -277,6 +280,8 @@ std::string validate(const pakr_system* s, const pakr_scene* sc, const float* x0
   if (p->workgroups_per_cu < 0 || p->workgroups_per_cu > 8) return "workgroups_per_cu must be 0..8";
   if (p->spec_tiles < -1 || p->spec_tiles > 1024) return "spec_tiles must be -1..1024";
   if (p->tier0_nodes < -1) return "tier0_nodes must be >= -1";
+  if (p->tier1_nodes < -1) return "tier1_nodes must be >= -1";
+  if (p->tier1_grid < 0 || p->tier1_grid == 1) return "tier1_grid must be 0 or >= 2";
   m = validate_scene(sc);
   if (!m.empty()) return m;
   *code = PAKR_E_GOAL_INVALID;
@@ -364,6 +369,32 @@ int tier0_nodes_for(const pakr_params& prm, const DevProblem& Q) {
   return t;
 }
 
+// The second tier of the tree: the first G1 workgroups plan while the tree has
+// at most tier1_nodes nodes.  Auto: G1 = the rollout workgroups of one batch,
+// at least 32, as a power of two; tier1_nodes = the largest of the paper's
+// tier sizes 4^k (k = 5..9) whose NN scan G1 workgroups do in about 20 000
+// cycles each (K x n x (2d + 1) / 64 / G1), if it lies above the first tier.
+// Off (0) where G1 would reach the whole grid.
+void tier1_for(const pakr_params& prm, DevProblem* Q) {
+  Q->tier1_nodes = 0;
+  Q->tier1_grid = 0;
+  if (prm.tier1_nodes < 0 || Q->G <= 2) return;
+  int g1 = prm.tier1_grid;
+  if (g1 <= 0) {
+    g1 = 32;
+    while (g1 < Q->G_roll) g1 <<= 1;
+  }
+  if (g1 >= Q->G) return;
+  int t1 = prm.tier1_nodes;
+  if (t1 == 0) {
+    for (int k = 5, v = 1024; k <= 9; ++k, v *= 4)
+      if ((double)Q->K * v * (2.0 * Q->d + 1.0) / WAVE / g1 <= 20000.0) t1 = v;
+  }
+  if (t1 <= Q->tier0_nodes) return;
+  Q->tier1_nodes = t1;
+  Q->tier1_grid = g1;
+}
+
 // The device record of one query planned by G workgroups with L lanes per candidate.
 DevProblem make_problem(const pakr_system& sys, const pakr_scene& scene, const pakr_goal& goal,
                         const pakr_params& prm, int G, int lanes, int rt = NT, int qt = 1) {
@@ -391,6 +422,7 @@ DevProblem make_problem(const pakr_system& sys, const pakr_scene& scene, const p
   Q.G_roll = (prm.B + Q.cpb - 1) / Q.cpb;
   Q.spec_tiles = spec_tiles_for(prm, Q, scene.n_box + scene.n_sphere);
   Q.tier0_nodes = tier0_nodes_for(prm, Q);
+  tier1_for(prm, &Q);
   Q.max_path_edges = prm.max_path_edges > 0 ? prm.max_path_edges : DEFAULT_PATH_EDGES;
   Q.obs_floats = obs_floats_of(P, scene.n_box, scene.n_sphere);
   Q.key0 = (uint32_t)(prm.seed & 0xffffffffull);

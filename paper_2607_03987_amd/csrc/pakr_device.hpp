@@ -38,7 +38,9 @@ struct DevProblem {
   int nn_tpg;                     // NN: threads per node group (NT / TPG groups)
   int spec_tiles;                 // tiles each idle workgroup scans ahead in phase 2 (0: none)
   int tier0_nodes;                // workgroup 0 plans alone while the tree has <= this many nodes
-  int pad_t;
+  int tier1_nodes;                // ... then the first tier1_grid workgroups up to this many
+  int tier1_grid;
+  int pad_t[3];
   uint32_t key0, key1;
   float dt, h_speed, c0, vnorm_max;
   float goal_r, goal_r2, edge_duration, pad0;
@@ -65,7 +67,8 @@ struct DevHeader {
   // hand-off of the loop from workgroup 0 (alone while the tree is in the
   // first tier) to the grid: word ((iterations done + 1) << 1 | call ended),
   // then the loop state that the resuming workgroups adopt
-  uint32_t join;
+  // ((iterations done + 1) << 32 | workgroups of the tier that starts << 1 | call ended)
+  unsigned long long join;
   int ho_rounds, ho_status;
   uint32_t ho_gen;
   long long ticks[8];                        // per-step device time of the last call

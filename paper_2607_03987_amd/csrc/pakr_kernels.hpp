@@ -234,19 +234,20 @@ struct Smem {
   LoopState* state;            // hand-off state read by waiting workgroups
 };
 
-// Loop state handed from workgroup 0 to the rest of a query's workgroups
-// when the tree leaves the first tier (see plan_loop).
+// Loop state handed from workgroup 0 to workgroups that join when the tree
+// grows into a tier with more workgroups (see plan_loop).
 struct LoopState {
   int n, round, iter, n_sol, rounds_done, status;
   float c_best;
   uint32_t gen;
   long long it_done;
   int ended;
+  int grid;  // workgroups of the tier that starts
 };
 
-// Workgroup 0 publishes the loop state; the resuming workgroups take the
-// next iteration (iterations done = it_done) from it, or leave if `ended`.
-// Every thread of the workgroup calls it.
+// Workgroup 0 publishes the loop state; the workgroups below st.grid that
+// wait take the next iteration (iterations done = it_done) from it, and all
+// waiting workgroups leave if `ended`.  Every thread of the workgroup calls it.
 __device__ __forceinline__ void publish_handoff(const KArgs& a, const LoopState& st) {
   __syncthreads();  // the whole workgroup's writes precede the release below
   if (threadIdx.x == 0) {
@@ -260,22 +261,34 @@ __device__ __forceinline__ void publish_handoff(const KArgs& a, const LoopState&
     h->ho_status = st.status;
     h->ho_gen = st.gen;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    const uint32_t w = ((uint32_t)(st.it_done + 1) << 1) | (uint32_t)(st.ended != 0);
+    const unsigned long long w = ((unsigned long long)(st.it_done + 1) << 32) |
+                                 ((unsigned long long)(uint32_t)st.grid << 1) |
+                                 (unsigned long long)(st.ended != 0);
     __hip_atomic_store(&h->join, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
-// A workgroup other than 0, which stopped at iteration `waited_at`, waits
-// until workgroup 0 publishes a hand-off made at or after it, and adopts
-// its state.  Returns false if the wait passed `deadline` (device clock).
-__device__ __forceinline__ bool await_handoff(const KArgs& a, long long waited_at,
+// Workgroup `b`, outside the tier of the iteration after `waited_at`
+// iterations, waits until workgroup 0 publishes a hand-off made at or after
+// it that starts a tier including b (or ends the call), and adopts its state.
+// Hand-offs to tiers that still exclude b are skipped without reading the
+// state (workgroup 0 may publish the next one meanwhile; a workgroup that
+// joins takes part in the next iteration's barriers, so no newer hand-off can
+// overwrite the state while it reads).  Returns false if the wait passed
+// `deadline` (device clock).
+__device__ __forceinline__ bool await_handoff(const KArgs& a, int b, long long waited_at,
                                               long long deadline, LoopState* s_st) {
   if (threadIdx.x == 0) {
     bool ok = true;
-    uint32_t w;
+    unsigned long long w, skipped = 0ull;
     while (true) {
       w = __hip_atomic_load(&a.hdr->join, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if ((long long)(w >> 1) > waited_at) break;
+      // (the call's end may be published at the same iteration count as a
+      // hand-off this workgroup skipped: only that exact word is skipped)
+      if ((long long)(w >> 32) > waited_at && w != skipped) {
+        if ((w & 1ull) != 0ull || b < (int)((w >> 1) & 0x7fffffffull)) break;
+        skipped = w;  // a tier without this workgroup: wait for a later one
+      }
       if (wall_clock64() > deadline) {
         ok = false;
         break;
@@ -293,8 +306,8 @@ __device__ __forceinline__ bool await_handoff(const KArgs& a, long long waited_a
       s_st->rounds_done = h->ho_rounds;
       s_st->status = h->ho_status;
       s_st->gen = h->ho_gen;
-      s_st->it_done = (long long)(w >> 1) - 1;
-      s_st->ended = (int)(w & 1u);
+      s_st->it_done = (long long)(w >> 32) - 1;
+      s_st->ended = (int)(w & 1ull);
     } else {
       s_st->ended = -1;
     }
@@ -308,13 +321,17 @@ __device__ __forceinline__ bool await_handoff(const KArgs& a, long long waited_a
 // targets per thread in the NN scan; GROUPED: the scan may split tiles into
 // node slices (P.nn_tpg threads per slice), else one target per thread.
 //
-// Tiers (the paper's memory tiers of the tree, Sec. IV-A): while the round's
-// tree has at most P.tier0_nodes nodes, workgroup 0 runs every step of the
-// iteration alone (G = 1: no grid barrier, no hand-over through memory
-// between workgroups) and the others wait; once it outgrows that tier, the
-// whole grid takes over from the state workgroup 0 hands over.  At a round
-// end that returns to the first tier, a grid barrier first puts every
-// workgroup's writes in memory, so workgroup 0 can reuse the slots alone.
+// Tiers (the paper's memory tiers of the tree, Sec. IV-A): the number of
+// workgroups that run an iteration grows with the round's tree -- workgroup 0
+// alone while it has at most P.tier0_nodes nodes (no grid barrier at all),
+// the first P.tier1_grid workgroups while it has at most P.tier1_nodes
+// (barriers among fewer workgroups are cheaper, and a small tree's NN scan
+// needs few), then all of them.  Workgroups outside the tier wait for a
+// hand-off.  When the tree grows into a larger tier, the tier's workgroups
+// meet at a barrier (their writes reach memory) and workgroup 0 publishes the
+// loop state; at a round end that returns to a smaller tier, a barrier of the
+// larger one first puts every participant's writes in memory, so fewer
+// workgroups can reuse the tree's slots.
 template <int SYS, int QT, bool GROUPED, bool TIERED>
 __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int G_all,
                                           const Smem& sm) {
@@ -382,23 +399,28 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
   }
   // both NN key buffers start cleared, and no hand-off is pending
   for (int k = b * NT + tid; k < 2 * K; k += G_all * NT) store_through(&a.nn_keys[k], ~0ull);
-  if (b == 0 && tid == 0) store_through(&a.hdr->join, 0u);
+  if (b == 0 && tid == 0) store_through(&a.hdr->join, 0ull);
   if (!grid_barrier(a, gen, &s_fail, b, G_all)) {
     if (tid == 0) __hip_atomic_store(&a.hdr->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return;
   }
   const int tier0 = (TIERED && G_all > 1) ? P.tier0_nodes : 0;
+  const int G1 = P.tier1_grid;
+  const int tier1 = (TIERED && G1 > 1 && G1 < G_all) ? P.tier1_nodes : 0;
+  // workgroups that run an iteration whose tree has nn nodes (same in all)
+  auto tier_grid = [&](int nn) { return nn <= tier0 ? 1 : (nn <= tier1 ? G1 : G_all); };
   // a waiting workgroup gives up at the call's guard time
   const long long wait_deadline = wall_clock64() + a.guard_ticks;
   LoopState* const s_st = sm.state;
+  bool failed = false;  // a grid barrier of the loop timed out
 
   while (true) {
     if (a.max_iters > 0 && it_done >= a.max_iters) { status |= PAKR_S_ITERS_DONE; break; }
     if (a.max_rounds > 0 && rounds_done >= a.max_rounds) { status |= PAKR_S_ROUNDS_DONE; break; }
-    // first tier: workgroup 0 alone (identical decision in every workgroup)
-    const bool solo = TIERED && n <= tier0;
-    if (solo && b != 0) {
-      if (!await_handoff(a, it_done, wait_deadline, s_st)) {
+    // the tree's tier decides who runs this iteration (identical in every workgroup)
+    const int G = TIERED ? tier_grid(n) : G_all;
+    if (b >= G) {
+      if (!await_handoff(a, b, it_done, wait_deadline, s_st)) {
         if (tid == 0) __hip_atomic_store(&a.hdr->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return;
       }
@@ -417,7 +439,6 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
       spec_lo = 0;
       continue;
     }
-    const int G = solo ? 1 : G_all;
     int* trace = (a.trace != nullptr && it_done < a.trace_iters) ? a.trace + it_done * a.trace_words
                                                                  : nullptr;
     const int n0 = n;
@@ -587,8 +608,8 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
       s_misc[0] = now >= bk.deadline ? 1 : (now >= bk.guard ? 2 : 0);
     }
     if (!grid_barrier(a, gen, &s_fail, b, G, &s_misc[0])) {
-      if (tid == 0) __hip_atomic_store(&a.hdr->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      return;
+      failed = true;
+      break;
     }
     if (s_misc[0] != 0) {
       status |= (s_misc[0] == 1) ? PAKR_S_BUDGET_EXPIRED : PAKR_S_DEVICE_ERROR;
@@ -735,8 +756,8 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
                                     n0 / TILE, nnk_next, nullptr);
     mark(3);
     if (!grid_barrier(a, gen, &s_fail, b, G)) {
-      if (tid == 0) __hip_atomic_store(&a.hdr->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      return;
+      failed = true;
+      break;
     }
 
     mark(4);
@@ -907,23 +928,40 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
       spec_lo = spec_on ? min(P.spec_tiles * n_idle, n0 / TILE) : 0;
     }
     ++it_done;
-    if (!TIERED) {
-    } else if (solo && n > tier0) {
-      // the tree left the first tier: the grid takes the next iteration over
-      const LoopState st = {n, round, iter, n_sol, (int)rounds_done, status, c_best, gen, it_done, 0};
-      publish_handoff(a, st);
-    } else if (!solo && n <= tier0) {
-      // back to the first tier (a new round): every workgroup's writes reach
-      // memory before workgroup 0 reuses the tree's slots alone
-      if (!grid_barrier(a, gen, &s_fail, b, G_all)) {
-        if (tid == 0) __hip_atomic_store(&a.hdr->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        return;
+    if (TIERED) {
+      const int G_next = tier_grid(n);
+      if (G_next != G) {
+        // a larger tier: this tier's writes reach memory (a barrier of its
+        // workgroups), then workgroup 0 wakes the workgroups that join; a
+        // smaller one (a new round): every participant's writes reach memory
+        // before fewer workgroups reuse the tree's slots
+        if (G > 1 && !grid_barrier(a, gen, &s_fail, b, G)) {
+          failed = true;
+          break;
+        }
+        if (G_next > G && b == 0) {
+          const LoopState st = {n, round, iter, n_sol, (int)rounds_done, status, c_best, gen,
+                                it_done, 0, G_next};
+          publish_handoff(a, st);
+        }
       }
     }
   }
-  // the others may be waiting for a hand-off: the call has ended
-  if (TIERED && b == 0 && tier0 > 0 && n <= tier0) {
-    const LoopState st = {n, round, iter, n_sol, (int)rounds_done, status, c_best, gen, it_done, 1};
+  if (failed) {
+    // every participant leaves; workgroup 0 also releases the workgroups that
+    // wait outside the tier (the plan is unusable: nothing more is written)
+    if (tid == 0) __hip_atomic_store(&a.hdr->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (TIERED && b == 0) {
+      const LoopState st = {n, round, iter, n_sol, (int)rounds_done, status, c_best, gen, it_done,
+                            1, G_all};
+      publish_handoff(a, st);
+    }
+    return;
+  }
+  // workgroups outside the last tier may be waiting for a hand-off: the call has ended
+  if (TIERED && b == 0 && tier_grid(n) < G_all) {
+    const LoopState st = {n, round, iter, n_sol, (int)rounds_done, status, c_best, gen, it_done, 1,
+                          G_all};
     publish_handoff(a, st);
   }
 

@@ -80,7 +80,7 @@ class Params(C.Structure):
                 ("query_id", C.c_uint32), ("max_iters_per_round", C.c_int), ("grid", C.c_int),
                 ("max_path_edges", C.c_int), ("lanes_per_candidate", C.c_int),
                 ("workgroups_per_cu", C.c_int), ("spec_tiles", C.c_int),
-                ("tier0_nodes", C.c_int)]
+                ("tier0_nodes", C.c_int), ("tier1_nodes", C.c_int), ("tier1_grid", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -228,7 +228,8 @@ class CQuery:
     """The C structs of one Problem (holds the host arrays alive)."""
 
     def __init__(self, prob: W.Problem, grid: int = 0, max_path_edges: int = 0, lanes: int = 0,
-                 wg_per_cu: int = 0, spec: int = 0, tier0: int = 0):
+                 wg_per_cu: int = 0, spec: int = 0, tier0: int = 0, tier1: int = 0,
+                 tier1_grid: int = 0):
         self.prob = prob
         s = System()
         s.id, s.d, s.m = prob.system, prob.d, prob.m
@@ -270,6 +271,8 @@ class CQuery:
         p.workgroups_per_cu = int(wg_per_cu)
         p.spec_tiles = int(spec)
         p.tier0_nodes = int(tier0)
+        p.tier1_nodes = int(tier1)
+        p.tier1_grid = int(tier1_grid)
         self.params = p
 
 
@@ -300,7 +303,8 @@ class Plan:
     """
 
     def __init__(self, prob: W.Problem, grid: int = 0, max_path_edges: int = 0, device=None,
-                 lanes: int = 0, wg_per_cu: int = 0, spec: int = 0, tier0: int = 0):
+                 lanes: int = 0, wg_per_cu: int = 0, spec: int = 0, tier0: int = 0,
+                 tier1: int = 0, tier1_grid: int = 0):
         import torch
 
         if not torch.cuda.is_available():
@@ -308,7 +312,8 @@ class Plan:
         self.torch = torch
         self.prob = prob
         self.q = CQuery(prob, grid=grid, max_path_edges=max_path_edges, lanes=lanes,
-                        wg_per_cu=wg_per_cu, spec=spec, tier0=tier0)
+                        wg_per_cu=wg_per_cu, spec=spec, tier0=tier0, tier1=tier1,
+                        tier1_grid=tier1_grid)
         self.device = torch.device(device or "cuda")
         nbytes = workspace_size(self.q)
         if nbytes == 0:

@@ -48,7 +48,7 @@ int main(void) {
          sizeof(pakr_solution), sizeof(pakr_refine_params));
   P(pakr_refine_params, delta); P(pakr_refine_params, u_ref); P(pakr_refine_params, u_scale);
   P(pakr_system, vnorm_max); P(pakr_scene, sph_r); P(pakr_params, cost_bound);
-  P(pakr_params, seed); P(pakr_params, max_path_edges); P(pakr_params, lanes_per_candidate); P(pakr_params, workgroups_per_cu); P(pakr_params, spec_tiles); P(pakr_params, tier0_nodes); P(pakr_stats, c_best);
+  P(pakr_params, seed); P(pakr_params, max_path_edges); P(pakr_params, lanes_per_candidate); P(pakr_params, workgroups_per_cu); P(pakr_params, spec_tiles); P(pakr_params, tier0_nodes); P(pakr_params, tier1_grid); P(pakr_stats, c_best);
   P(pakr_stats, call_iters); P(pakr_stats, insert_ms); P(pakr_stats, step_ms); P(pakr_stats, clock_end_ms); P(pakr_stats, near_ties_goal); P(pakr_solution, t_ms);
   return 0;
 }
@@ -108,7 +108,8 @@ def test_plan_init_rejects_malformed_queries(mutate, code):
     assert _init_code(mutate(W.config_c1())) == code
 
 
-@pytest.mark.parametrize("kw", [dict(spec=-2), dict(spec=1025), dict(tier0=-2)])
+@pytest.mark.parametrize("kw", [dict(spec=-2), dict(spec=1025), dict(tier0=-2), dict(tier1=-2),
+                                dict(tier1_grid=1), dict(tier1_grid=-1)])
 def test_plan_init_rejects_bad_scan_ahead_and_tier_settings(kw):
     q = pakr.CQuery(W.config_c1(), **kw)
     with pytest.raises(pakr.PakrError) as e:

@@ -189,45 +189,60 @@ def test_free_running_against_reference():
         assert rel_err([s["cost"] for s in sg], [s["cost"] for s in so]).max() <= 1e-4
 
 
-@pytest.mark.parametrize("cfg,kw,iters,tier0", [
-    ("c1", dict(seed=7, max_iters_per_round=45), 90, 0),
-    ("c1", dict(seed=7, max_iters_per_round=45), 90, 256),
-    ("c1", dict(seed=7, max_iters_per_round=45), 90, -1),
-    ("c2", dict(seed=2, B=1024, A=8, n_cap=60000, max_iters_per_round=25), 40, 0),
+C1_LAUNCH = dict(seed=7, max_iters_per_round=45)
+
+
+@pytest.mark.parametrize("cfg,kw,iters,tiers", [
+    ("c1", C1_LAUNCH, 90, dict()),
+    ("c1", C1_LAUNCH, 90, dict(tier0=256, tier1=-1)),
+    ("c1", C1_LAUNCH, 90, dict(tier0=-1, tier1=-1)),
+    # all three tiers: 1 workgroup, then 8, then the grid, and back at each round
+    ("c1", C1_LAUNCH, 90, dict(tier0=256, tier1=1024, tier1_grid=8)),
+    ("c1", C1_LAUNCH, 90, dict(tier0=-1, tier1=2048, tier1_grid=32)),
+    ("c2", dict(seed=2, B=1024, A=8, n_cap=60000, max_iters_per_round=25), 40, dict(tier1=-1)),
+    ("c2", dict(seed=2, B=1024, A=8, n_cap=60000, max_iters_per_round=25), 40,
+     dict(tier1=4096, tier1_grid=64)),
 ])
-def test_one_launch_of_many_iterations_against_reference(cfg, kw, iters, tier0):
+def test_one_launch_of_many_iterations_against_reference(cfg, kw, iters, tiers):
     """All iterations in one launch: workgroups without a rollout chunk scan
-    ahead for the next iteration and phase 1 skips what they covered, and
-    (c1) workgroup 0 runs the iterations alone while the tree is in the first
-    tier, handing over to the grid and back at every round; every
-    iteration's record is replayed in the reference, re-seeded with the tree
-    the records rebuild."""
+    ahead for the next iteration and phase 1 skips what they covered, and the
+    tiers of the tree (workgroup 0 alone, then tier1_grid workgroups, then the
+    grid) hand the loop over as the tree grows and take it back at every
+    round; every iteration's record is replayed in the reference, re-seeded
+    with the tree the records rebuild."""
     prob = W.CONFIGS[cfg](**kw)
-    print(f"case {prob.name} one launch of {iters} iterations, tier0 {tier0}", flush=True)
-    plan = pakr.Plan(prob, tier0=tier0)
+    print(f"case {prob.name} one launch of {iters} iterations, tiers {tiers}", flush=True)
+    plan = pakr.Plan(prob, **tiers)
     traces = plan.expand(iters, trace=True)
     replay_records(prob, traces, oracle.OraclePlan(prob), ctx=f"{prob.name} launch")
     rounds = {tr["round"] for tr in traces}
     sizes = [tr["n0"] for tr in traces]
     assert len(rounds) >= 2, "the run should cross a round end"
-    if tier0 > 0:
-        # both tiers, in more than one round
-        assert min(sizes) <= tier0 < max(sizes)
+    for key in ("tier0", "tier1"):
+        if tiers.get(key, 0) > 0:
+            # the tree crosses the tier's bound, in more than one round
+            assert min(sizes) <= tiers[key] < max(sizes), key
     plan.close()
 
 
 @pytest.mark.parametrize("cfg,kw,tiers", [
-    ("c1", dict(max_iters_per_round=80), (-1, 256, 1024, 4096, 0, 1 << 20)),
-    # a first tier whose rollout takes several passes of workgroup 0
-    ("c2", dict(B=1024, A=8, n_cap=60000, max_iters_per_round=40), (-1, 4096, 0)),
+    ("c1", dict(max_iters_per_round=80),
+     (dict(tier0=-1, tier1=-1), dict(tier0=256, tier1=-1), dict(tier0=1024, tier1=-1),
+      dict(tier0=4096, tier1=-1), dict(), dict(tier0=1 << 20), dict(tier0=-1, tier1=1 << 20),
+      dict(tier0=256, tier1=4096, tier1_grid=2), dict(tier0=1024, tier1=16384, tier1_grid=64))),
+    # a first tier whose rollout takes several passes of workgroup 0, and a
+    # second tier below the rollout workgroups of one batch
+    ("c2", dict(B=1024, A=8, n_cap=60000, max_iters_per_round=40),
+     (dict(tier0=-1, tier1=-1), dict(tier0=4096), dict(), dict(tier0=-1, tier1=16384, tier1_grid=4),
+      dict(tier0=1024, tier1=16384, tier1_grid=96))),
 ])
 def test_tiers_do_not_change_results(cfg, kw, tiers):
-    """Where the first tier ends (never, 4^4 .. 4^6 nodes, auto, always)
-    changes no result."""
+    """Where the tiers end and how many workgroups the second one has (none,
+    4^4 .. 4^8 nodes, auto, always) changes no result."""
     prob = W.CONFIGS[cfg](**kw)
     res = []
     for t in tiers:
-        p = pakr.Plan(prob, tier0=t)
+        p = pakr.Plan(prob, **t)
         p.replan(max_rounds=3)
         st = p.status()
         res.append((st["total_iters"], st["insertions"], st["nn_pairs"],
@@ -290,24 +305,28 @@ def test_extracted_path_is_feasible():
     assert all(b["cost"] < a["cost"] for a, b in zip(sols, sols[1:]))
 
 
-@pytest.mark.parametrize("cfg,grid,tier0", [("c2", 0, 0), ("c2", 3, 0), ("c2", 1, 0),
-                                            ("c1", 0, 1 << 20), ("c1", 0, 1024)])
-def test_budget_stop_ends_every_workgroup_at_one_iteration(cfg, grid, tier0):
+@pytest.mark.parametrize("cfg,grid,tiers", [
+    ("c2", 0, dict()), ("c2", 3, dict()), ("c2", 1, dict()),
+    ("c2", 0, dict(tier1=16384, tier1_grid=64)),
+    ("c1", 0, dict(tier0=1 << 20)), ("c1", 0, dict(tier0=1024, tier1=-1)), ("c1", 0, dict()),
+    ("c1", 0, dict(tier0=256, tier1=4096, tier1_grid=16)), ("c1", 0, dict(tier0=-1, tier1=1 << 20)),
+])
+def test_budget_stop_ends_every_workgroup_at_one_iteration(cfg, grid, tiers):
     """Workgroup 0 takes the budget decision and every workgroup leaves at the
-    same iteration -- also when it runs the first tier alone while the others
-    wait (c1: always, or in the first tier of each round): the tree then
-    equals that of a call capped at the same number of iterations, and
-    planning resumes from it."""
+    same iteration -- also when only a tier's workgroups run while the others
+    wait (c1: workgroup 0 alone or a sub-grid, always or in the small tiers
+    of each round): the tree then equals that of a call capped at the same
+    number of iterations, and planning resumes from it."""
     prob = (W.config_c2(B=512, A=8, n_cap=200000) if cfg == "c2"
             else W.config_c1(max_iters_per_round=60))
-    print(f"case {cfg} budget 15 ms grid {grid} tier0 {tier0}", flush=True)
-    a = pakr.Plan(prob, grid=grid, tier0=tier0)
+    print(f"case {cfg} budget 15 ms grid {grid} tiers {tiers}", flush=True)
+    a = pakr.Plan(prob, grid=grid, **tiers)
     a.replan(budget_ms=15.0)
     st = a.status()
     assert st["status"] & pakr.S_BUDGET_EXPIRED, st["status"]
     assert st["call_iters"] > 0
     assert 15.0 <= st["call_ms"] <= 15.0 + 10.0, st["call_ms"]
-    b = pakr.Plan(prob, grid=grid, tier0=tier0)
+    b = pakr.Plan(prob, grid=grid, **tiers)
     b.replan(max_iters=st["call_iters"])
     sb = b.status()
     assert sb["status"] & pakr.S_ITERS_DONE and not sb["status"] & pakr.S_BUDGET_EXPIRED
