@@ -173,15 +173,22 @@ typedef struct pakr_params {
                                       (a power of 4 from the query's sizes), -1 = none.
                                       Single-query plans only: a batch's team always plans
                                       together                                            */
-  int tier1_nodes;                 /* second tier: while a round's tree has more than
-                                      tier0_nodes and at most this many nodes, only the first
-                                      tier1_grid workgroups run each iteration (their
-                                      barriers are cheaper; results do not depend on it);
-                                      0 = auto (a power of 4 from the query's sizes), -1 =
+  int tier1_nodes;                 /* sub-grid tiers beyond the first: while a round's tree
+                                      has more than tier0_nodes nodes and fits a sub-grid
+                                      tier, only that tier's first workgroups run each
+                                      iteration (their barriers are cheaper; results do not
+                                      depend on it).  0 = auto: grids doubling from
+                                      tier1_grid up to the whole grid, each taking the trees
+                                      whose NN scan costs each of its workgroups at most
+                                      tier_scan_cycles; > 0 = one sub-grid tier of
+                                      tier1_grid workgroups up to this many nodes; -1 =
                                       none.  Single-query plans only                      */
-  int tier1_grid;                  /* workgroups of the second tier, 0 = auto (at least
-                                      the rollout workgroups of one batch and 32), else
-                                      2..grid                                             */
+  int tier1_grid;                  /* workgroups of the first sub-grid tier, 0 = auto (at
+                                      least the rollout workgroups of one batch and 32, a
+                                      power of two), else 2..grid                         */
+  int tier_scan_cycles;            /* auto sub-grid tiers: the NN scan cycles per workgroup
+                                      and iteration (K x nodes x (2d + 1) / 64 / workgroups)
+                                      up to which a tier keeps the tree; 0 = 10000        */
 } pakr_params;
 
 typedef struct pakr_stats {
@@ -219,6 +226,12 @@ typedef struct pakr_stats {
    * signed margin; they are not counted here.) */
   long long near_ties_prune;
   long long near_ties_goal;
+  /* The plan's tiers of the tree: while a round's tree has at most tier_nodes[k]
+   * nodes, only the first tier_grid[k] workgroups run an iteration (ascending;
+   * unused entries 0; larger trees use all `grid` workgroups).  A first tier
+   * has tier_grid 1.  All 0 for a batch's queries. */
+  int tier_nodes[8];
+  int tier_grid[8];
 } pakr_stats;
 
 typedef struct pakr_solution {

@@ -100,9 +100,6 @@ int lanes_for(const pakr_params& p, int n_obs, int grid_limit) {
   return L;
 }
 
-// (defined below make_problem's helpers)
-void tier1_for(const pakr_params& prm, DevProblem* Q);
-
 // Rollout threads per workgroup.  A candidate's rollout is one serial chain
 // per lane; when that chain is long (car, quadrotor: trigonometry in every
 // evaluation of f) half the workgroup takes candidates, so each SIMD runs one
@@ -282,6 +279,7 @@ std::string validate(const pakr_system* s, const pakr_scene* sc, const float* x0
   if (p->tier0_nodes < -1) return "tier0_nodes must be >= -1";
   if (p->tier1_nodes < -1) return "tier1_nodes must be >= -1";
   if (p->tier1_grid < 0 || p->tier1_grid == 1) return "tier1_grid must be 0 or >= 2";
+  if (p->tier_scan_cycles < 0) return "tier_scan_cycles must be >= 0";
   m = validate_scene(sc);
   if (!m.empty()) return m;
   *code = PAKR_E_GOAL_INVALID;
@@ -369,30 +367,44 @@ int tier0_nodes_for(const pakr_params& prm, const DevProblem& Q) {
   return t;
 }
 
-// The second tier of the tree: the first G1 workgroups plan while the tree has
-// at most tier1_nodes nodes.  Auto: G1 = the rollout workgroups of one batch,
-// at least 32, as a power of two; tier1_nodes = the largest of the paper's
-// tier sizes 4^k (k = 5..9) whose NN scan G1 workgroups do in about 20 000
-// cycles each (K x n x (2d + 1) / 64 / G1), if it lies above the first tier.
-// Off (0) where G1 would reach the whole grid.
-void tier1_for(const pakr_params& prm, DevProblem* Q) {
-  Q->tier1_nodes = 0;
-  Q->tier1_grid = 0;
+// Sub-grid tiers of the tree: the first tier_grid[k] workgroups plan while the
+// tree has at most tier_nodes[k] nodes.  Auto: grids doubling from G1 = the
+// rollout workgroups of one batch (at least 32, a power of two) up to the
+// whole grid; tier k takes the trees whose NN scan costs each of its
+// workgroups at most S cycles (K x n x (2d + 1) / 64 / grid, S =
+// tier_scan_cycles, 10 000 by default: about what the rollout phase of the
+// small-batch systems hides), so the grid grows with the tree, and a tier
+// that already holds the tree's capacity is the last.  An explicit tier1_nodes gives one
+// sub-grid tier of G1 workgroups instead.
+void tiers_for(const pakr_params& prm, DevProblem* Q) {
+  for (int k = 0; k < MAX_TIERS; ++k) Q->tier_nodes[k] = Q->tier_grid[k] = 0;
   if (prm.tier1_nodes < 0 || Q->G <= 2) return;
-  int g1 = prm.tier1_grid;
-  if (g1 <= 0) {
-    g1 = 32;
-    while (g1 < Q->G_roll) g1 <<= 1;
+  int g = prm.tier1_grid;
+  if (g <= 0) {
+    g = 32;
+    while (g < Q->G_roll) g <<= 1;
   }
-  if (g1 >= Q->G) return;
-  int t1 = prm.tier1_nodes;
-  if (t1 == 0) {
-    for (int k = 5, v = 1024; k <= 9; ++k, v *= 4)
-      if ((double)Q->K * v * (2.0 * Q->d + 1.0) / WAVE / g1 <= 20000.0) t1 = v;
+  if (g >= Q->G) return;
+  if (prm.tier1_nodes > 0) {
+    if (prm.tier1_nodes <= Q->tier0_nodes) return;
+    Q->tier_nodes[0] = prm.tier1_nodes;
+    Q->tier_grid[0] = g;
+    return;
   }
-  if (t1 <= Q->tier0_nodes) return;
-  Q->tier1_nodes = t1;
-  Q->tier1_grid = g1;
+  const double S = prm.tier_scan_cycles > 0 ? prm.tier_scan_cycles : 10000.0;
+  const double per_node = (double)Q->K * (2.0 * Q->d + 1.0) / WAVE;  // cycles per node and workgroup
+  int k = 0, prev = Q->tier0_nodes;
+  for (; g < Q->G && k < MAX_TIERS; g <<= 1) {
+    const double lim = std::min(S * g / per_node, (double)Q->n_cap);
+    int nk = (int)lim;
+    if (nk < Q->n_cap) nk -= nk % TILE;
+    if (nk <= prev) continue;
+    Q->tier_nodes[k] = nk;
+    Q->tier_grid[k] = g;
+    ++k;
+    prev = nk;
+    if (nk >= Q->n_cap) break;
+  }
 }
 
 // The device record of one query planned by G workgroups with L lanes per candidate.
@@ -422,7 +434,7 @@ DevProblem make_problem(const pakr_system& sys, const pakr_scene& scene, const p
   Q.G_roll = (prm.B + Q.cpb - 1) / Q.cpb;
   Q.spec_tiles = spec_tiles_for(prm, Q, scene.n_box + scene.n_sphere);
   Q.tier0_nodes = tier0_nodes_for(prm, Q);
-  tier1_for(prm, &Q);
+  tiers_for(prm, &Q);
   Q.max_path_edges = prm.max_path_edges > 0 ? prm.max_path_edges : DEFAULT_PATH_EDGES;
   Q.obs_floats = obs_floats_of(P, scene.n_box, scene.n_sphere);
   Q.key0 = (uint32_t)(prm.seed & 0xffffffffull);
@@ -901,6 +913,16 @@ int pakr_status(pakr_plan* pl, pakr_stats* out) {
   int rc = sync_header(pl, &h);
   if (rc != PAKR_OK) return rc;
   fill_stats(h, pl->ticks_per_ms, pl->G, out);
+  const DevProblem& P = pl->args.P;
+  int k = 0;
+  if (P.tier0_nodes > 0) {
+    out->tier_nodes[k] = P.tier0_nodes;
+    out->tier_grid[k++] = 1;
+  }
+  for (int i = 0; i < MAX_TIERS && P.tier_nodes[i] > 0; ++i) {
+    out->tier_nodes[k] = P.tier_nodes[i];
+    out->tier_grid[k++] = P.tier_grid[i];
+  }
   return PAKR_OK;
 }
 

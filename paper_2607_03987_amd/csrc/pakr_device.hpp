@@ -21,6 +21,7 @@ constexpr int WAVE = 64;
 constexpr float NEAR_TIE = 1e-5f;
 constexpr int MAX_SOLUTIONS = 1024;
 constexpr int MAX_GR = 1024;     // rollout workgroups per iteration
+constexpr int MAX_TIERS = 6;     // sub-grid tiers of the tree (grids 32 .. 1024 doubling)
 constexpr int VAL_FLOATS = 32;   // validity record held in LDS (see load_validity)
 
 enum : int { F_VALID = 1, F_PRUNE_OK = 2, F_KEEP = 4, F_GOAL = 8 };
@@ -38,9 +39,11 @@ struct DevProblem {
   int nn_tpg;                     // NN: threads per node group (NT / TPG groups)
   int spec_tiles;                 // tiles each idle workgroup scans ahead in phase 2 (0: none)
   int tier0_nodes;                // workgroup 0 plans alone while the tree has <= this many nodes
-  int tier1_nodes;                // ... then the first tier1_grid workgroups up to this many
-  int tier1_grid;
-  int pad_t[3];
+  // then the first tier_grid[k] workgroups while it has <= tier_nodes[k] (both ascending;
+  // unused entries 0); beyond the last bound the whole grid
+  int tier_nodes[MAX_TIERS];
+  int tier_grid[MAX_TIERS];
+  int pad_t;
   uint32_t key0, key1;
   float dt, h_speed, c0, vnorm_max;
   float goal_r, goal_r2, edge_duration, pad0;

@@ -324,7 +324,7 @@ __device__ __forceinline__ bool await_handoff(const KArgs& a, int b, long long w
 // Tiers (the paper's memory tiers of the tree, Sec. IV-A): the number of
 // workgroups that run an iteration grows with the round's tree -- workgroup 0
 // alone while it has at most P.tier0_nodes nodes (no grid barrier at all),
-// the first P.tier1_grid workgroups while it has at most P.tier1_nodes
+// the first P.tier_grid[k] workgroups while it has at most P.tier_nodes[k]
 // (barriers among fewer workgroups are cheaper, and a small tree's NN scan
 // needs few), then all of them.  Workgroups outside the tier wait for a
 // hand-off.  When the tree grows into a larger tier, the tier's workgroups
@@ -405,10 +405,14 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
     return;
   }
   const int tier0 = (TIERED && G_all > 1) ? P.tier0_nodes : 0;
-  const int G1 = P.tier1_grid;
-  const int tier1 = (TIERED && G1 > 1 && G1 < G_all) ? P.tier1_nodes : 0;
   // workgroups that run an iteration whose tree has nn nodes (same in all)
-  auto tier_grid = [&](int nn) { return nn <= tier0 ? 1 : (nn <= tier1 ? G1 : G_all); };
+  auto tier_grid = [&](int nn) {
+    if (nn <= tier0) return 1;
+#pragma unroll
+    for (int k = 0; k < MAX_TIERS; ++k)
+      if (nn <= P.tier_nodes[k]) return min(P.tier_grid[k], G_all);
+    return G_all;
+  };
   // a waiting workgroup gives up at the call's guard time
   const long long wait_deadline = wall_clock64() + a.guard_ticks;
   LoopState* const s_st = sm.state;

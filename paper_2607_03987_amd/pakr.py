@@ -80,7 +80,8 @@ class Params(C.Structure):
                 ("query_id", C.c_uint32), ("max_iters_per_round", C.c_int), ("grid", C.c_int),
                 ("max_path_edges", C.c_int), ("lanes_per_candidate", C.c_int),
                 ("workgroups_per_cu", C.c_int), ("spec_tiles", C.c_int),
-                ("tier0_nodes", C.c_int), ("tier1_nodes", C.c_int), ("tier1_grid", C.c_int)]
+                ("tier0_nodes", C.c_int), ("tier1_nodes", C.c_int), ("tier1_grid", C.c_int),
+                ("tier_scan_cycles", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -93,7 +94,8 @@ class Stats(C.Structure):
                 ("nn_ms", C.c_double), ("rollout_ms", C.c_double), ("insert_ms", C.c_double),
                 ("step_ms", C.c_double * 6), ("clock_start_ms", C.c_double),
                 ("clock_end_ms", C.c_double), ("near_ties_prune", C.c_longlong),
-                ("near_ties_goal", C.c_longlong)]
+                ("near_ties_goal", C.c_longlong), ("tier_nodes", C.c_int * 8),
+                ("tier_grid", C.c_int * 8)]
 
 
 class Solution(C.Structure):
@@ -229,7 +231,7 @@ class CQuery:
 
     def __init__(self, prob: W.Problem, grid: int = 0, max_path_edges: int = 0, lanes: int = 0,
                  wg_per_cu: int = 0, spec: int = 0, tier0: int = 0, tier1: int = 0,
-                 tier1_grid: int = 0):
+                 tier1_grid: int = 0, tier_scan: int = 0):
         self.prob = prob
         s = System()
         s.id, s.d, s.m = prob.system, prob.d, prob.m
@@ -273,7 +275,15 @@ class CQuery:
         p.tier0_nodes = int(tier0)
         p.tier1_nodes = int(tier1)
         p.tier1_grid = int(tier1_grid)
+        p.tier_scan_cycles = int(tier_scan)
         self.params = p
+
+
+def _stats_dict(s: "Stats") -> dict:
+    out = {f[0]: getattr(s, f[0]) for f in Stats._fields_}
+    for k in ("step_ms", "tier_nodes", "tier_grid"):
+        out[k] = list(out[k])
+    return out
 
 
 def workspace_size(q: CQuery) -> int:
@@ -304,7 +314,7 @@ class Plan:
 
     def __init__(self, prob: W.Problem, grid: int = 0, max_path_edges: int = 0, device=None,
                  lanes: int = 0, wg_per_cu: int = 0, spec: int = 0, tier0: int = 0,
-                 tier1: int = 0, tier1_grid: int = 0):
+                 tier1: int = 0, tier1_grid: int = 0, tier_scan: int = 0):
         import torch
 
         if not torch.cuda.is_available():
@@ -313,7 +323,7 @@ class Plan:
         self.prob = prob
         self.q = CQuery(prob, grid=grid, max_path_edges=max_path_edges, lanes=lanes,
                         wg_per_cu=wg_per_cu, spec=spec, tier0=tier0, tier1=tier1,
-                        tier1_grid=tier1_grid)
+                        tier1_grid=tier1_grid, tier_scan=tier_scan)
         self.device = torch.device(device or "cuda")
         nbytes = workspace_size(self.q)
         if nbytes == 0:
@@ -361,9 +371,7 @@ class Plan:
     def status(self) -> dict:
         s = Stats()
         _check(load().pakr_status(self.h, C.byref(s)), self.h)
-        out = {f[0]: getattr(s, f[0]) for f in Stats._fields_}
-        out["step_ms"] = list(out["step_ms"])
-        return out
+        return _stats_dict(s)
 
     def solutions(self) -> list:
         n = C.c_int(0)
@@ -563,9 +571,7 @@ class BatchPlan:
     def status(self, q: int) -> dict:
         s = Stats()
         _bcheck(load().pakr_batch_status(self.h, q, C.byref(s)), self.h)
-        out = {f[0]: getattr(s, f[0]) for f in Stats._fields_}
-        out["step_ms"] = list(out["step_ms"])
-        return out
+        return _stats_dict(s)
 
     def solutions(self, q: int) -> list:
         n = C.c_int(0)

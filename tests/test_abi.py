@@ -48,8 +48,8 @@ int main(void) {
          sizeof(pakr_solution), sizeof(pakr_refine_params));
   P(pakr_refine_params, delta); P(pakr_refine_params, u_ref); P(pakr_refine_params, u_scale);
   P(pakr_system, vnorm_max); P(pakr_scene, sph_r); P(pakr_params, cost_bound);
-  P(pakr_params, seed); P(pakr_params, max_path_edges); P(pakr_params, lanes_per_candidate); P(pakr_params, workgroups_per_cu); P(pakr_params, spec_tiles); P(pakr_params, tier0_nodes); P(pakr_params, tier1_grid); P(pakr_stats, c_best);
-  P(pakr_stats, call_iters); P(pakr_stats, insert_ms); P(pakr_stats, step_ms); P(pakr_stats, clock_end_ms); P(pakr_stats, near_ties_goal); P(pakr_solution, t_ms);
+  P(pakr_params, seed); P(pakr_params, max_path_edges); P(pakr_params, lanes_per_candidate); P(pakr_params, workgroups_per_cu); P(pakr_params, spec_tiles); P(pakr_params, tier0_nodes); P(pakr_params, tier1_grid); P(pakr_params, tier_scan_cycles); P(pakr_stats, c_best);
+  P(pakr_stats, call_iters); P(pakr_stats, insert_ms); P(pakr_stats, step_ms); P(pakr_stats, clock_end_ms); P(pakr_stats, near_ties_goal); P(pakr_stats, tier_grid); P(pakr_solution, t_ms);
   return 0;
 }
 """
@@ -109,7 +109,7 @@ def test_plan_init_rejects_malformed_queries(mutate, code):
 
 
 @pytest.mark.parametrize("kw", [dict(spec=-2), dict(spec=1025), dict(tier0=-2), dict(tier1=-2),
-                                dict(tier1_grid=1), dict(tier1_grid=-1)])
+                                dict(tier1_grid=1), dict(tier1_grid=-1), dict(tier_scan=-1)])
 def test_plan_init_rejects_bad_scan_ahead_and_tier_settings(kw):
     q = pakr.CQuery(W.config_c1(), **kw)
     with pytest.raises(pakr.PakrError) as e:

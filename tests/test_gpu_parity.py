@@ -192,22 +192,28 @@ def test_free_running_against_reference():
 C1_LAUNCH = dict(seed=7, max_iters_per_round=45)
 
 
-@pytest.mark.parametrize("cfg,kw,iters,tiers", [
-    ("c1", C1_LAUNCH, 90, dict()),
-    ("c1", C1_LAUNCH, 90, dict(tier0=256, tier1=-1)),
-    ("c1", C1_LAUNCH, 90, dict(tier0=-1, tier1=-1)),
-    # all three tiers: 1 workgroup, then 8, then the grid, and back at each round
-    ("c1", C1_LAUNCH, 90, dict(tier0=256, tier1=1024, tier1_grid=8)),
-    ("c1", C1_LAUNCH, 90, dict(tier0=-1, tier1=2048, tier1_grid=32)),
-    ("c2", dict(seed=2, B=1024, A=8, n_cap=60000, max_iters_per_round=25), 40, dict(tier1=-1)),
+@pytest.mark.parametrize("cfg,kw,iters,tiers,cross", [
+    ("c1", C1_LAUNCH, 90, dict(), 0),
+    ("c1", C1_LAUNCH, 90, dict(tier0=256, tier1=-1), 1),
+    ("c1", C1_LAUNCH, 90, dict(tier0=-1, tier1=-1), 0),
+    # three tiers: 1 workgroup, then 8, then the grid, and back at each round
+    ("c1", C1_LAUNCH, 90, dict(tier0=256, tier1=1024, tier1_grid=8), 2),
+    ("c1", C1_LAUNCH, 90, dict(tier0=-1, tier1=2048, tier1_grid=32), 1),
+    # the auto table with a small scan budget: 1, 32, 64, 128 workgroups, then the grid
+    ("c1", C1_LAUNCH, 90, dict(tier0=128, tier_scan=120), 4),
+    # ... and 8, 16, 32, 64, 128, then the grid
+    ("c1", C1_LAUNCH, 90, dict(tier0=-1, tier1_grid=8, tier_scan=120), 5),
+    ("c2", dict(seed=2, B=1024, A=8, n_cap=60000, max_iters_per_round=25), 40, dict(tier1=-1), 0),
     ("c2", dict(seed=2, B=1024, A=8, n_cap=60000, max_iters_per_round=25), 40,
-     dict(tier1=4096, tier1_grid=64)),
+     dict(tier1=4096, tier1_grid=64), 1),
+    ("c2", dict(seed=2, B=1024, A=8, n_cap=60000, max_iters_per_round=25), 40,
+     dict(tier_scan=1000), 2),
 ])
-def test_one_launch_of_many_iterations_against_reference(cfg, kw, iters, tiers):
+def test_one_launch_of_many_iterations_against_reference(cfg, kw, iters, tiers, cross):
     """All iterations in one launch: workgroups without a rollout chunk scan
     ahead for the next iteration and phase 1 skips what they covered, and the
-    tiers of the tree (workgroup 0 alone, then tier1_grid workgroups, then the
-    grid) hand the loop over as the tree grows and take it back at every
+    tiers of the tree (workgroup 0 alone, then sub-grids of growing size, then
+    the grid) hand the loop over as the tree grows and take it back at every
     round; every iteration's record is replayed in the reference, re-seeded
     with the tree the records rebuild."""
     prob = W.CONFIGS[cfg](**kw)
@@ -218,10 +224,65 @@ def test_one_launch_of_many_iterations_against_reference(cfg, kw, iters, tiers):
     rounds = {tr["round"] for tr in traces}
     sizes = [tr["n0"] for tr in traces]
     assert len(rounds) >= 2, "the run should cross a round end"
-    for key in ("tier0", "tier1"):
-        if tiers.get(key, 0) > 0:
-            # the tree crosses the tier's bound, in more than one round
-            assert min(sizes) <= tiers[key] < max(sizes), key
+    st = plan.status()
+    bounds = [b for b in st["tier_nodes"] if b > 0]
+    assert len(bounds) >= cross, st["tier_nodes"]
+    for bound in bounds[:cross]:
+        # the tree grows across the tier's bound (and the round end takes it back)
+        assert min(sizes) <= bound < max(sizes), (bound, max(sizes))
+    plan.close()
+
+
+def _auto_tiers(prob, G, g1, scan, tier0):
+    """The auto table of sub-grid tiers, from its definition: grids doubling
+    from g1 below the whole grid G, each taking the trees whose NN scan costs
+    each of its workgroups at most `scan` cycles (K n (2d + 1) / 64 / grid),
+    in whole tiles below the tree's capacity; empty bounds are dropped."""
+    K = prob.B // prob.A
+    out, prev, g = [], tier0, g1
+    while g < G and len(out) < 6:
+        lim = min(scan * g / (K * (2 * prob.d + 1) / 64), prob.n_cap)
+        nk = int(lim)
+        if nk < prob.n_cap:
+            nk -= nk % 64
+        if nk > prev:
+            out.append((nk, g))
+            prev = nk
+            if nk >= prob.n_cap:
+                break
+        g *= 2
+    return out
+
+
+@pytest.mark.parametrize("cfg,kw,tiers", [
+    ("c1", dict(), dict(tier1_grid=32)),
+    ("c1", dict(), dict(tier0=-1, tier1_grid=8, tier_scan=120)),
+    ("c1", dict(), dict(tier0=128, tier1_grid=32, tier_scan=120)),
+    ("c2", dict(B=1024, A=8, n_cap=60000), dict(tier1_grid=32, tier_scan=1000)),
+    ("c2", dict(), dict(tier1_grid=64)),
+    ("uni1", dict(), dict(tier1_grid=32)),
+    ("acrobot", dict(), dict(tier1_grid=64)),
+    ("c1", dict(), dict(tier0=-1, tier1=3000, tier1_grid=16)),
+])
+def test_tier_table(cfg, kw, tiers):
+    """The tier table a plan reports is the one its rule defines (first tier
+    of one workgroup, then the sub-grid tiers, ascending)."""
+    prob = (W.CONFIGS.get(cfg) or W.MORE_CONFIGS[cfg])(**kw)
+    plan = pakr.Plan(prob, **tiers)
+    st = plan.status()
+    table = [(n, g) for n, g in zip(st["tier_nodes"], st["tier_grid"]) if n > 0]
+    t0 = [e for e in table if e[1] == 1]
+    tier0 = t0[0][0] if t0 else 0
+    if tiers.get("tier0", 0) > 0:
+        assert tier0 == tiers["tier0"]
+    if tiers.get("tier1", 0) > 0:
+        want = [(tiers["tier1"], tiers["tier1_grid"])]
+    else:
+        want = _auto_tiers(prob, st["grid"], tiers["tier1_grid"], tiers.get("tier_scan") or 10000,
+                           tier0)
+    print(f"{prob.name} grid {st['grid']} tiers {table}", flush=True)
+    assert table == t0 + want
+    assert all(a[0] < b[0] and a[1] < b[1] for a, b in zip(table, table[1:]))
     plan.close()
 
 
@@ -229,12 +290,13 @@ def test_one_launch_of_many_iterations_against_reference(cfg, kw, iters, tiers):
     ("c1", dict(max_iters_per_round=80),
      (dict(tier0=-1, tier1=-1), dict(tier0=256, tier1=-1), dict(tier0=1024, tier1=-1),
       dict(tier0=4096, tier1=-1), dict(), dict(tier0=1 << 20), dict(tier0=-1, tier1=1 << 20),
-      dict(tier0=256, tier1=4096, tier1_grid=2), dict(tier0=1024, tier1=16384, tier1_grid=64))),
+      dict(tier0=256, tier1=4096, tier1_grid=2), dict(tier0=1024, tier1=16384, tier1_grid=64),
+      dict(tier_scan=120), dict(tier0=-1, tier1_grid=2, tier_scan=60))),
     # a first tier whose rollout takes several passes of workgroup 0, and a
     # second tier below the rollout workgroups of one batch
     ("c2", dict(B=1024, A=8, n_cap=60000, max_iters_per_round=40),
      (dict(tier0=-1, tier1=-1), dict(tier0=4096), dict(), dict(tier0=-1, tier1=16384, tier1_grid=4),
-      dict(tier0=1024, tier1=16384, tier1_grid=96))),
+      dict(tier0=1024, tier1=16384, tier1_grid=96), dict(tier_scan=1000))),
 ])
 def test_tiers_do_not_change_results(cfg, kw, tiers):
     """Where the tiers end and how many workgroups the second one has (none,
@@ -310,6 +372,7 @@ def test_extracted_path_is_feasible():
     ("c2", 0, dict(tier1=16384, tier1_grid=64)),
     ("c1", 0, dict(tier0=1 << 20)), ("c1", 0, dict(tier0=1024, tier1=-1)), ("c1", 0, dict()),
     ("c1", 0, dict(tier0=256, tier1=4096, tier1_grid=16)), ("c1", 0, dict(tier0=-1, tier1=1 << 20)),
+    ("c1", 0, dict(tier0=-1, tier1_grid=8, tier_scan=120)),
 ])
 def test_budget_stop_ends_every_workgroup_at_one_iteration(cfg, grid, tiers):
     """Workgroup 0 takes the budget decision and every workgroup leaves at the
