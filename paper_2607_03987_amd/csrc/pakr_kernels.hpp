@@ -84,8 +84,21 @@ __device__ __forceinline__ void store_through(T* p, T v) {
 // the release word as soon as it has seen all flags and only then takes its own acquire
 // (L2 invalidate) for the reads that follow.  One wave per workgroup runs the
 // acquire; the workgroup barrier after it orders the other waves' reads.
+template <typename Work>
+__device__ __forceinline__ bool grid_barrier_with(const KArgs& a, uint32_t& gen, int* s_fail,
+                                                  int wg, int G, int* s_note, Work&& work);
+
 __device__ __forceinline__ bool grid_barrier(const KArgs& a, uint32_t& gen, int* s_fail, int wg,
                                              int G, int* s_note = nullptr) {
+  return grid_barrier_with(a, gen, s_fail, wg, G, s_note, [](uint32_t) {});
+}
+
+// The barrier above; a workgroup other than the collector runs work(target)
+// (every thread) after raising its flag and before it waits for the release
+// (target: the generation the release word will carry).
+template <typename Work>
+__device__ __forceinline__ bool grid_barrier_with(const KArgs& a, uint32_t& gen, int* s_fail,
+                                                  int wg, int G, int* s_note, Work&& work) {
   ++gen;
   __syncthreads();
   if (G == 1) return true;
@@ -118,10 +131,14 @@ __device__ __forceinline__ bool grid_barrier(const KArgs& a, uint32_t& gen, int*
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-  } else if (threadIdx.x == 0) {
-    *s_fail = 0;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __hip_atomic_store(&a.bar_flags[wg], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    if (threadIdx.x == 0) {
+      *s_fail = 0;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_store(&a.bar_flags[wg], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    work(target);
+    if (threadIdx.x == 0) {
     const long long limit = wall_clock64() + a.barrier_timeout_ticks;
     while (true) {
       const uint32_t v = __hip_atomic_load(&a.hdr->release, __ATOMIC_RELAXED,
@@ -138,6 +155,7 @@ __device__ __forceinline__ bool grid_barrier(const KArgs& a, uint32_t& gen, int*
       __builtin_amdgcn_s_sleep(1);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
   }
   __syncthreads();
   return *s_fail == 0;
@@ -375,6 +393,9 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
   long long it_done = 0, rounds_done = 0;
   int status = 0;
   int spec_lo = 0;  // tiles [0, spec_lo) already scanned for this iteration's targets
+  // this workgroup's first pre_n own tiles of this iteration's scan were
+  // scanned while it waited at the previous iteration's second barrier
+  int pre_n = 0;
 
   // workgroup-0 bookkeeping, kept by its thread 0 in LDS
   Books& bk = *sm.books;
@@ -441,6 +462,7 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
       gen = (uint32_t)uni((int)s_st->gen);
       it_done = (long long)uni((int)s_st->it_done);
       spec_lo = 0;
+      pre_n = 0;
       continue;
     }
     int* trace = (a.trace != nullptr && it_done < a.trace_iters) ? a.trace + it_done * a.trace_words
@@ -465,11 +487,16 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
     // is folded into `keys` by device-scope atomic min.  With trace_q set,
     // workgroup 0 records the targets (drawn even if it scans nothing).
     const int TPG = GROUPED ? P.nn_tpg : NT, NG = NT / TPG, SL = TILE / NG;
+    // With stop_word set (one target chunk only), the scan also ends before a
+    // tile once that word carries generation stop_gen in its upper bits (the
+    // word is read one tile ahead); returns the tiles it scanned.
     auto nn_scan = [&](uint32_t it_q, int t0, int tstep, int tcount, int t_end,
-                       unsigned long long* keys, int* trace_q) {
+                       unsigned long long* keys, int* trace_q,
+                       const uint32_t* stop_word = nullptr, uint32_t stop_gen = 0) -> int {
       const bool scans = tcount > 0 && t0 < t_end;
       const bool record = trace_q != nullptr && b == 0;
-      if (!scans && !record) return;
+      if (!scans && !record) return 0;
+      int done = 0;
       int tid_nn = tid;
       asm volatile("" : "+v"(tid_nn));  // derived per call, not held across the loop
       const int grp = tid_nn / TPG, tl = tid_nn - grp * TPG;
@@ -537,9 +564,17 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
         fetch(t0);
         const int i0 = grp * SL;
         int t = t0;
+        uint32_t seen = 0u;  // the stop word as thread 0 last read it
+        if (stop_word != nullptr && tid == 0)
+          seen = __hip_atomic_load(stop_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         for (int cnt = 0; cnt < tcount && t < t_end; ++cnt, t += tstep) {
           const int node0 = t * TILE;
           __syncthreads();
+          if (stop_word != nullptr) {
+            if (tid == 0) s_misc[1] = (seen >> 3) == stop_gen;
+            __syncthreads();
+            if (s_misc[1]) break;
+          }
 #pragma unroll
           for (int r = 0; r < PF; ++r) {
             const int idx = tid + r * NT;
@@ -547,6 +582,9 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
           }
           __syncthreads();
           if (cnt + 1 < tcount && t + tstep < t_end) fetch(t + tstep);
+          if (stop_word != nullptr && tid == 0)
+            seen = __hip_atomic_load(stop_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ++done;
 #pragma unroll 2
           for (int i = i0; i < i0 + SL; i += 4) {
             float4 pc[D];
@@ -591,6 +629,7 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
           for (int k = tid; k < kc; k += NT) atomicMin(&keys[base + k], s_key[k]);
         }
       }
+      return done;
     };
 
     // ---------------- phase 1: targets + nearest neighbour -----------------
@@ -599,7 +638,7 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
     // scanned for these targets by the previous iteration's idle workgroups;
     // a tree of the root alone needs no scan (its only node is the parent).
     if (n0 > 1) {
-      const int t_first = spec_lo + ((b - spec_lo) % G + G) % G;
+      const int t_first = spec_lo + ((b - spec_lo) % G + G) % G + pre_n * G;
       nn_scan((uint32_t)iter, t_first, G, INT_MAX, ntiles, nnk, trace);
     } else {
       nn_scan((uint32_t)iter, 0, G, 0, 0, nnk, trace);
@@ -759,7 +798,21 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
     if (spec_on && b >= GR) nn_scan((uint32_t)(iter + 1), b - GR, n_idle, P.spec_tiles,
                                     n0 / TILE, nnk_next, nullptr);
     mark(3);
-    if (!grid_barrier(a, gen, &s_fail, b, G)) {
+    // While it waits at this barrier, a workgroup other than the collector
+    // scans its own full tiles for the next iteration's targets, in the order
+    // the next phase 1 would, until the release arrives: those tiles do not
+    // change in the insertion phase, and the next phase 1 starts after them.
+    // (The minimum is idempotent: how far it gets changes no result.)
+    const int spec_next = spec_on ? min(P.spec_tiles * n_idle, n0 / TILE) : 0;
+    const bool pre_ok = b != 0 && n0 > 1 && iter + 1 < P.max_iters_per_round && K <= TPG * QT;
+    int pre_done = 0;
+    auto prescan = [&](uint32_t target) {
+      if (!pre_ok) return;
+      const int t_next = spec_next + ((b - spec_next) % G + G) % G;
+      pre_done = nn_scan((uint32_t)(iter + 1), t_next, G, INT_MAX, n0 / TILE, nnk_next, nullptr,
+                         &a.hdr->release, target);
+    };
+    if (!grid_barrier_with(a, gen, &s_fail, b, G, nullptr, prescan)) {
       failed = true;
       break;
     }
@@ -926,15 +979,18 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
       n = 1;
       ++rounds_done;
       spec_lo = 0;
+      pre_n = 0;
     } else {
       ++iter;
       n = n1;
-      spec_lo = spec_on ? min(P.spec_tiles * n_idle, n0 / TILE) : 0;
+      spec_lo = spec_next;
+      pre_n = pre_done;
     }
     ++it_done;
     if (TIERED) {
       const int G_next = tier_grid(n);
       if (G_next != G) {
+        pre_n = 0;  // (the tiles' owners change with the grid)
         // a larger tier: this tier's writes reach memory (a barrier of its
         // workgroups), then workgroup 0 wakes the workgroups that join; a
         // smaller one (a new round): every participant's writes reach memory
