@@ -496,6 +496,13 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
       const bool scans = tcount > 0 && t0 < t_end;
       const bool record = trace_q != nullptr && b == 0;
       if (!scans && !record) return 0;
+      if (stop_word != nullptr) {  // (released already: draw no targets)
+        if (tid == 0)
+          s_misc[1] = (__hip_atomic_load(stop_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> 3) ==
+                      stop_gen;
+        __syncthreads();
+        if (s_misc[1]) return 0;
+      }
       int done = 0;
       int tid_nn = tid;
       asm volatile("" : "+v"(tid_nn));  // derived per call, not held across the loop
@@ -564,6 +571,7 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
         fetch(t0);
         const int i0 = grp * SL;
         int t = t0;
+        const int done0 = done;
         uint32_t seen = 0u;  // the stop word as thread 0 last read it
         if (stop_word != nullptr && tid == 0)
           seen = __hip_atomic_load(stop_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -613,6 +621,7 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
             }
           }
         }
+        if (done == done0) continue;  // stopped before any tile: nothing to fold
         if (direct) {
           if (tid < kc) atomicMin(&keys[base + tid], pack_key(bd[0], (uint32_t)bi[0]));
         } else {
