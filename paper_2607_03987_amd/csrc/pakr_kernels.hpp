@@ -139,22 +139,22 @@ __device__ __forceinline__ bool grid_barrier_with(const KArgs& a, uint32_t& gen,
     }
     work(target);
     if (threadIdx.x == 0) {
-    const long long limit = wall_clock64() + a.barrier_timeout_ticks;
-    while (true) {
-      const uint32_t v = __hip_atomic_load(&a.hdr->release, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-      if ((v >> 3) == target) {
-        *s_fail = (int)(v & 1u);
-        if (s_note != nullptr) *s_note = (int)((v >> 1) & 3u);
-        break;
+      const long long limit = wall_clock64() + a.barrier_timeout_ticks;
+      while (true) {
+        const uint32_t v = __hip_atomic_load(&a.hdr->release, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+        if ((v >> 3) == target) {
+          *s_fail = (int)(v & 1u);
+          if (s_note != nullptr) *s_note = (int)((v >> 1) & 3u);
+          break;
+        }
+        if (wall_clock64() > limit) {
+          *s_fail = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
       }
-      if (wall_clock64() > limit) {
-        *s_fail = 1;
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
   }
   __syncthreads();
@@ -497,9 +497,11 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
       const bool record = trace_q != nullptr && b == 0;
       if (!scans && !record) return 0;
       if (stop_word != nullptr) {  // (released already: draw no targets)
-        if (tid == 0)
-          s_misc[1] = (__hip_atomic_load(stop_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> 3) ==
-                      stop_gen;
+        if (tid == 0) {
+          const uint32_t w =
+              __hip_atomic_load(stop_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          s_misc[1] = (w >> 3) == stop_gen;
+        }
         __syncthreads();
         if (s_misc[1]) return 0;
       }
@@ -644,8 +646,10 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
     // ---------------- phase 1: targets + nearest neighbour -----------------
     // Tile t (64 nodes) belongs to workgroup t mod G, which writes it in the
     // insertion phase and scans it here.  Tiles [0, spec_lo) were already
-    // scanned for these targets by the previous iteration's idle workgroups;
-    // a tree of the root alone needs no scan (its only node is the parent).
+    // scanned for these targets by the previous iteration's idle workgroups,
+    // and this workgroup's next pre_n own tiles by itself while it waited at
+    // the previous barrier; a tree of the root alone needs no scan (its only
+    // node is the parent).
     if (n0 > 1) {
       const int t_first = spec_lo + ((b - spec_lo) % G + G) % G + pre_n * G;
       nn_scan((uint32_t)iter, t_first, G, INT_MAX, ntiles, nnk, trace);
