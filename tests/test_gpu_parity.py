@@ -101,11 +101,27 @@ def test_near_tie_counters():
     dict(B=256, A=1, n_cap=3000),          # A = 1
     dict(B=256, A=4, n_cap=300),           # the tree fills up
     dict(B=256, A=4, max_iters_per_round=3),  # iteration cap ends rounds
+    dict(B=1, A=1, n_cap=2000),            # one candidate per iteration
+    dict(T=1),                             # edges of a single RK4 step
 ])
 def test_step_parity_edge_cases(kw):
     prob = W.config_c1(**kw)
     print(f"case c1 {kw}", flush=True)
     step_parity(prob, 12, log=_log)
+
+
+def test_step_parity_start_inside_goal():
+    # the goal test applies to new nodes (Alg. 1), so a start inside the goal
+    # region ends the first rounds at their first iteration, each lowering the
+    # bound; once no child can beat it, every candidate is pruned and the tree
+    # stays at the root (no survivors at all)
+    prob = W.config_c1(n_cap=4000)
+    prob = prob.replace(goal_c=np.float32(prob.x_init[:2]))
+    print("case c1 start inside goal", flush=True)
+    step_parity(prob, 8, log=_log)
+    ref = oracle.OraclePlan(prob)
+    ends = [ref.iterate() for _ in range(8)]
+    assert ends[0].goal_j >= 0 and ends[-1].n1 == 1  # the case covers both regimes
 
 
 def test_step_parity_no_obstacles_and_small_grid():
