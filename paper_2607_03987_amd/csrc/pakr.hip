@@ -341,13 +341,21 @@ int nn_tpg_for(int K, int qt) {
 // phase takes -- a tile costs ~K (2d + 1) cycles of one CU (d subtractions
 // and d FMAs per target and node, 64 nodes over 64 lanes), the rollout ~4
 // cycles per instruction of a lane's serial chain per resident rollout wave,
-// plus the wait for the slowest chunk.
+// plus the wait for the slowest chunk.  A double integrator's chain is its
+// lane's share of the edge (di_edge: sub-steps and obstacles split over the
+// candidate's lanes, plus ~14 per step for the path length).
 int spec_tiles_for(const pakr_params& prm, const DevProblem& Q, int n_obs) {
   if (prm.spec_tiles < 0 || Q.G <= Q.G_roll) return 0;
   if (prm.spec_tiles > 0) return prm.spec_tiles;
   const double tile = (double)Q.K * (2.0 * Q.d + 1.0);
-  const double chain =
+  double chain =
       (double)Q.T * (12.0 * Q.d + 4.0 * f_eval_of(Q.system) + 3.0 * Q.npos * n_obs / Q.lanes);
+  if (Q.system == PAKR_DI2 || Q.system == PAKR_DI3) {
+    long long best = LLONG_MAX;
+    for (int ls = 1; ls <= Q.lanes; ls <<= 1)
+      best = std::min(best, di_lane_cost(Q.T, Q.lanes, n_obs, ls, DI_CH));
+    chain = (double)best + (Q.cost_kind == PAKR_COST_PATH_LENGTH ? 14.0 * Q.T : 0.0);
+  }
   const double waves = std::max(1.0, (double)(Q.cpb * Q.lanes) / (4.0 * WAVE));
   const double roll = chain * 4.0 * waves + 4000.0;
   return std::max(1, std::min(64, (int)(roll / tile)));

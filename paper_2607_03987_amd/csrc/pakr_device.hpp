@@ -451,6 +451,98 @@ __device__ __forceinline__ bool any_obstacle_hit(const float (&pos)[CH][NP], con
   return hit;
 }
 
+// One double-integrator edge shared by the L lanes of its candidate.  The RK4
+// map of these systems is their exact flow (rk4_step), so the state after s
+// steps is p0 + t v0 + (t^2/2) u, v0 + t u at t = s h: any lane can evaluate
+// any sub-step directly, and the same expression gives the same bits in every
+// lane.  Lane lg takes sub-steps s = 1 + (lg mod LS), then every LS-th, in
+// chunks of CH (a chunk past T repeats its first sub-step), and tests them
+// against obstacles lg / LS, then every (L / LS)-th; the caller ORs the lanes'
+// verdicts.  With the path-length cost every lane sums all T segment lengths
+// in step order, so neither the cost nor the verdict depends on the split.
+// On return x holds the state after T steps; `bad` is set if a tested
+// sub-step leaves the limits or hits an obstacle.
+template <int SYS, int CH>
+__device__ __forceinline__ void di_edge(const DevProblem& P, const float* s_val, const float* s_obs,
+                                        float* x, const float* u, int lg, int L, int LS,
+                                        bool path_len, float& len, bool& bad) {
+  constexpr int D = Sys<SYS>::D, NP = D / 2;
+  const float h = P.dt;
+  const int T = P.T;
+  auto state_at = [&](int s, float* xs) {
+    const float t = (float)s * h, th = 0.5f * t * t;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      xs[i] = x[i] + t * x[NP + i] + th * u[i];
+      xs[NP + i] = x[NP + i] + t * u[i];
+    }
+  };
+  const int ls = lg & (LS - 1), lo = lg / LS, LO = L / LS;
+  bool ok = true, hit = false;
+  for (int s0 = ls + 1; s0 <= T; s0 += CH * LS) {
+    float pos[CH][NP];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int s = s0 + c * LS <= T ? s0 + c * LS : s0;
+      float xs[D];
+      state_at(s, xs);
+      ok = ok & limits_ok<SYS>(s_val, xs);
+#pragma unroll
+      for (int k = 0; k < NP; ++k) pos[c][k] = xs[k];
+    }
+    hit = hit | any_obstacle_hit<NP, CH>(pos, s_obs, P.n_box, P.n_sph, lo, LO);
+  }
+  if (path_len) {
+    float prev[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) prev[k] = x[k];
+    for (int s = 1; s <= T; ++s) {
+      float xs[D];
+      state_at(s, xs);
+      float s2 = 0.0f;
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        const float e = xs[k] - prev[k];
+        s2 += e * e;
+        prev[k] = xs[k];
+      }
+      len += __builtin_amdgcn_sqrtf(s2);  // v_sqrt_f32 (1 ulp)
+    }
+  }
+  float xe[D];
+  state_at(T, xe);
+#pragma unroll
+  for (int i = 0; i < D; ++i) x[i] = xe[i];
+  bad = hit | !ok;
+}
+
+constexpr int DI_CH = 5;  // sub-steps per lane and obstacle sweep in di_edge
+
+// Per-lane work of di_edge with LS sub-step groups (instructions, roughly:
+// each evaluated sub-step ~16 for its state and limits, each obstacle test
+// ~11, chunks of ch sub-steps counted whole).  The kernel picks the LS with
+// the least; the host prices the rollout phase with it.
+__host__ __device__ inline long long di_lane_cost(int T, int L, int n_obs, int ls, int ch) {
+  const int lo = L / ls;
+  const long long steps = (long long)(((T + ls - 1) / ls + ch - 1) / ch) * ch;
+  return steps * (16 + 11 * ((n_obs + lo - 1) / lo));
+}
+
+// Sub-step groups LS (a power of two dividing L) for di_edge.
+template <int CH>
+__device__ __forceinline__ int di_step_groups(const DevProblem& P, int L) {
+  int best_ls = 1;
+  long long best = LLONG_MAX;
+  for (int ls = 1; ls <= L; ls <<= 1) {
+    const long long c = di_lane_cost(P.T, L, P.n_box + P.n_sph, ls, CH);
+    if (c < best) {
+      best = c;
+      best_ls = ls;
+    }
+  }
+  return best_ls;
+}
+
 template <int SYS>
 __device__ __forceinline__ float goal_dist2(const DevProblem& P, const float* x) {
   constexpr int NP = Sys<SYS>::P;

@@ -373,6 +373,10 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
   const int B = P.B, A = P.A, K = P.K, GR = P.G_roll;
   const int L = P.lanes, CPB = P.cpb;   // lanes per candidate, candidates per rollout workgroup
   const int S = GR * CPB;
+  // double integrators: a candidate's lanes split its sub-steps (LS groups)
+  // and the obstacles (L / LS groups) instead of each integrating the edge
+  constexpr bool DI = SYS == PAKR_DI2 || SYS == PAKR_DI3;
+  const int LS = DI ? di_step_groups<DI_CH>(P, L) : 1;
   const size_t NC = (size_t)P.n_cap;
 
   float* stg_x = a.stg;
@@ -681,7 +685,8 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
       mark(2);
 
       // L consecutive lanes share candidate j: each integrates the edge and
-      // tests every L-th obstacle; the group ORs its hits
+      // tests every L-th obstacle (double integrators: di_edge's split of
+      // sub-steps and obstacles); the group ORs its hits
       // (only the first L * CPB threads take candidates: with half the
       // workgroup, each SIMD runs one rollout wave)
       const int lg = tid % L;
@@ -707,32 +712,38 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
         const bool path_len = P.cost_kind == PAKR_COST_PATH_LENGTH;
         constexpr int CH = Sys<SYS>::CH;
         bool lim_ok = true;
-        // integrate CH steps, then test their CH positions against this
-        // lane's obstacles in one sweep (each obstacle read once per chunk)
-        for (int t0 = 0; t0 < P.T; t0 += CH) {
-          float pos[CH][NP];
+        if constexpr (DI) {
+          bool bad = false;
+          di_edge<SYS, DI_CH>(P, s_val, s_obs, x, u, lg, L, LS, path_len, len, bad);
+          lim_ok = !bad;
+        } else {
+          // integrate CH steps, then test their CH positions against this
+          // lane's obstacles in one sweep (each obstacle read once per chunk)
+          for (int t0 = 0; t0 < P.T; t0 += CH) {
+            float pos[CH][NP];
 #pragma unroll
-          for (int s = 0; s < CH; ++s) {
-            if (t0 + s < P.T) {
-              float xp[NP];
+            for (int s = 0; s < CH; ++s) {
+              if (t0 + s < P.T) {
+                float xp[NP];
 #pragma unroll
-              for (int c = 0; c < NP; ++c) xp[c] = x[c];
-              rk4_step<SYS>(P, x, u, P.dt);
-              if (path_len) {
-                float s2 = 0.0f;
+                for (int c = 0; c < NP; ++c) xp[c] = x[c];
+                rk4_step<SYS>(P, x, u, P.dt);
+                if (path_len) {
+                  float s2 = 0.0f;
 #pragma unroll
-                for (int c = 0; c < NP; ++c) {
-                  const float e = x[c] - xp[c];
-                  s2 += e * e;
+                  for (int c = 0; c < NP; ++c) {
+                    const float e = x[c] - xp[c];
+                    s2 += e * e;
+                  }
+                  len += __builtin_amdgcn_sqrtf(s2);  // v_sqrt_f32 (1 ulp)
                 }
-                len += __builtin_amdgcn_sqrtf(s2);  // v_sqrt_f32 (1 ulp)
+                lim_ok = lim_ok & limits_ok<SYS>(s_val, x);
               }
-              lim_ok = lim_ok & limits_ok<SYS>(s_val, x);
-            }
 #pragma unroll
-            for (int c = 0; c < NP; ++c) pos[s][c] = x[c];  // past T: repeats the last state
+              for (int c = 0; c < NP; ++c) pos[s][c] = x[c];  // past T: repeats the last state
+            }
+            hit = hit | any_obstacle_hit<NP, CH>(pos, s_obs, P.n_box, P.n_sph, lg, L);
           }
-          hit = hit | any_obstacle_hit<NP, CH>(pos, s_obs, P.n_box, P.n_sph, lg, L);
         }
         hit = hit | !lim_ok;
         cost = c_par + (path_len ? len : P.edge_duration);

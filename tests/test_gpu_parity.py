@@ -156,6 +156,15 @@ def test_step_parity_lanes_per_candidate(cfg, kw, lanes):
     step_parity(prob, 6, lanes=lanes, log=_log)
 
 
+@pytest.mark.parametrize("lanes", [16, 8])
+def test_step_parity_ragged_sub_step_split(lanes):
+    # T = 23 leaves the lanes of a double-integrator candidate unequal shares
+    # of sub-steps and partly filled sweeps
+    prob = W.config_c2(B=1024, A=8, n_cap=30000, T=23)
+    print(f"case c2 T 23 lanes {lanes}", flush=True)
+    step_parity(prob, 6, lanes=lanes, log=_log)
+
+
 def test_expand_in_pieces_equals_one_call():
     prob = W.config_c1()
     a = pakr.Plan(prob)
@@ -186,6 +195,28 @@ def test_replan_is_deterministic_and_launch_shape_independent():
     for r in res[1:]:
         assert r[0] == res[0][0] and r[1] == res[0][1] and r[2] == res[0][2]
         for x, y in zip(r[3], res[0][3]):
+            np.testing.assert_array_equal(x, y)
+
+
+@pytest.mark.parametrize("cfg,kw", [("c2", dict(B=1024, A=8, n_cap=40000, max_iters_per_round=40)),
+                                    ("c1", dict(T=23, max_iters_per_round=60))])
+def test_double_integrator_lane_split_does_not_change_results(cfg, kw):
+    """Double integrators split each edge's sub-steps and obstacles over the
+    candidate's lanes in a way that depends on the lane count (and T): the
+    trees must still be identical, bit for bit."""
+    prob = W.CONFIGS[cfg](**kw)
+    res = []
+    for lanes in (1, 4, 16, 2):
+        p = pakr.Plan(prob, lanes=lanes)
+        p.replan(max_rounds=2)
+        st = p.status()
+        res.append((st["total_iters"], [s["cost"] for s in p.solutions()], p.copy_tree()))
+        print(f"{prob.name} lanes {lanes}: {st['total_iters']} iters, {len(res[-1][1])} "
+              f"solutions", flush=True)
+        p.close()
+    for r in res[1:]:
+        assert r[0] == res[0][0] and r[1] == res[0][1]
+        for x, y in zip(r[2], res[0][2]):
             np.testing.assert_array_equal(x, y)
 
 
