@@ -400,6 +400,10 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
   // this workgroup's first pre_n own tiles of this iteration's scan were
   // scanned while it waited at the previous iteration's second barrier
   int pre_n = 0;
+  // this workgroup's share of the last insertion, when its copy waits for
+  // the next iteration's NN scan: slots [pend_n0, pend_n1) (see nn_scan)
+  int pend_n0 = 0, pend_n1 = 0;
+  int* pend_trace = nullptr;
 
   // workgroup-0 bookkeeping, kept by its thread 0 in LDS
   Books& bk = *sm.books;
@@ -494,12 +498,67 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
     // With stop_word set (one target chunk only), the scan also ends before a
     // tile once that word carries generation stop_gen in its upper bits (the
     // word is read one tile ahead); returns the tiles it scanned.
+    // With do_copy, the scan first completes this workgroup's pending copy of
+    // the last insertion: each of its new slots (one per thread) is loaded
+    // from the staging area before the targets are drawn and stored just
+    // before the first scanned tile that holds new slots is fetched, so the
+    // loads' latency passes behind the target draw and the earlier tiles.
     auto nn_scan = [&](uint32_t it_q, int t0, int tstep, int tcount, int t_end,
                        unsigned long long* keys, int* trace_q,
-                       const uint32_t* stop_word = nullptr, uint32_t stop_gen = 0) -> int {
+                       const uint32_t* stop_word = nullptr, uint32_t stop_gen = 0,
+                       bool do_copy = false) -> int {
+      int cp_s = -1, cp_par = 0, cp_j = 0;
+      float cp_x[D], cp_u[M], cp_c = 0.0f;
+      int kt = 0;  // index of the first scanned tile that holds new slots
+      if (do_copy) {
+        const int t_lo = pend_n0 / TILE, t_hi = (pend_n1 - 1) / TILE;
+        const int t_f = t_lo + ((b - t_lo % G) % G + G) % G;
+        const int n_my = t_f <= t_hi ? (t_hi - t_f) / G + 1 : 0;
+        if (tid < n_my * TILE) {
+          const int sl = (t_f + (tid / TILE) * G) * TILE + (tid % TILE);
+          if (sl >= pend_n0 && sl < pend_n1) {
+            const int r = sl - pend_n0;
+            int lo = 0, hi = GR - 1;
+            while (lo < hi) {
+              const int mid = (lo + hi + 1) >> 1;
+              if (s_off[mid] <= r) lo = mid; else hi = mid - 1;
+            }
+            const int e = lo * CPB + (r - s_off[lo]);
+#pragma unroll
+            for (int c = 0; c < D; ++c) cp_x[c] = stg_x[(size_t)c * S + e];
+#pragma unroll
+            for (int c = 0; c < M; ++c) cp_u[c] = stg_u[(size_t)c * S + e];
+            cp_par = stg_par[e];
+            cp_c = stg_c[e];
+            if (pend_trace != nullptr) cp_j = stg_j[e];
+            cp_s = sl;
+          }
+        }
+        kt = t_lo <= t0 ? 0 : (t_lo - t0 + tstep - 1) / tstep;
+      }
+      bool copied = !do_copy;
+      auto store_copy = [&]() {
+        if (cp_s >= 0) {
+#pragma unroll
+          for (int c = 0; c < D; ++c) a.states[(size_t)c * NC + cp_s] = cp_x[c];
+#pragma unroll
+          for (int c = 0; c < M; ++c) a.actions[(size_t)c * NC + cp_s] = cp_u[c];
+          a.parents[cp_s] = cp_par;
+          a.costs[cp_s] = cp_c;
+          if (pend_trace != nullptr) {
+            TraceView tv(pend_trace, K, B, D, M);
+            tv.slots[cp_j] = cp_s;
+          }
+        }
+        __syncthreads();  // the workgroup's reads of these slots come after
+        copied = true;
+      };
       const bool scans = tcount > 0 && t0 < t_end;
       const bool record = trace_q != nullptr && b == 0;
-      if (!scans && !record) return 0;
+      if (!scans && !record) {
+        if (!copied) store_copy();
+        return 0;
+      }
       if (stop_word != nullptr) {  // (released already: draw no targets)
         if (tid == 0) {
           const uint32_t w =
@@ -546,7 +605,10 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
             for (int c = 0; c < D; ++c) q[0][c] = 0.0f;
           }
         }
-        if (!scans) continue;
+        if (!scans) {
+          if (!copied) store_copy();
+          continue;
+        }
         float bd[QT];
         int bi[QT];
 #pragma unroll
@@ -574,6 +636,7 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
                                                         : 3.0e38f;
           }
         };
+        if (!copied && kt == 0) store_copy();
         fetch(t0);
         const int i0 = grp * SL;
         int t = t0;
@@ -595,6 +658,7 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
             if (idx < D * TILE) (&s_tile[0][0])[idx] = pre[r];
           }
           __syncthreads();
+          if (!copied && cnt + 1 == kt) store_copy();
           if (cnt + 1 < tcount && t + tstep < t_end) fetch(t + tstep);
           if (stop_word != nullptr && tid == 0)
             seen = __hip_atomic_load(stop_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -627,6 +691,7 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
             }
           }
         }
+        if (!copied) store_copy();  // (no scanned tile holds new slots)
         if (done == done0) continue;  // stopped before any tile: nothing to fold
         if (direct) {
           if (tid < kc) atomicMin(&keys[base + tid], pack_key(bd[0], (uint32_t)bi[0]));
@@ -656,7 +721,9 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
     // node is the parent).
     if (n0 > 1) {
       const int t_first = spec_lo + ((b - spec_lo) % G + G) % G + pre_n * G;
-      nn_scan((uint32_t)iter, t_first, G, INT_MAX, ntiles, nnk, trace);
+      nn_scan((uint32_t)iter, t_first, G, INT_MAX, ntiles, nnk, trace, nullptr, 0,
+              pend_n1 > pend_n0);
+      pend_n0 = pend_n1 = 0;
     } else {
       nn_scan((uint32_t)iter, 0, G, 0, 0, nnk, trace);
     }
@@ -859,34 +926,6 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
     const int survivors = s_off[GR];
     const int n_ins = min(survivors, P.n_cap - n0);
     const int n1 = n0 + n_ins;
-    if (n_ins > 0) {
-      // this workgroup owns tiles t = b (mod G); copy the survivors that land there
-      const int t_lo = n0 / TILE, t_hi = (n1 - 1) / TILE;
-      const int t_first = t_lo + ((b - t_lo % G) % G + G) % G;
-      const int n_my = t_first <= t_hi ? (t_hi - t_first) / G + 1 : 0;
-      for (int idx = tid; idx < n_my * TILE; idx += NT) {
-        const int s = (t_first + (idx / TILE) * G) * TILE + (idx % TILE);
-        if (s >= n0 && s < n1) {
-          const int r = s - n0;
-          int lo = 0, hi = GR - 1;
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_off[mid] <= r) lo = mid; else hi = mid - 1;
-          }
-          const int e = lo * CPB + (r - s_off[lo]);
-#pragma unroll
-          for (int c = 0; c < D; ++c) a.states[(size_t)c * NC + s] = stg_x[(size_t)c * S + e];
-#pragma unroll
-          for (int c = 0; c < M; ++c) a.actions[(size_t)c * NC + s] = stg_u[(size_t)c * S + e];
-          a.parents[s] = stg_par[e];
-          a.costs[s] = stg_c[e];
-          if (trace != nullptr) {
-            TraceView tv(trace, K, B, D, M);
-            tv.slots[stg_j[e]] = s;
-          }
-        }
-      }
-    }
     // cheapest inserted goal candidate, ties to the lowest j
     unsigned long long key = n_ins == survivors ? gall : ~0ull;
     for (int w = n_ins == survivors ? GR : tid; w < GR; w += NT) {
@@ -928,6 +967,49 @@ __device__ __forceinline__ void plan_loop(const KArgs& a, const int b, const int
     if (goal) end = END_GOAL;
     else if (n1 >= P.n_cap) end = END_TREE_FULL;
     else if (iter + 1 >= P.max_iters_per_round) end = END_ITER_CAP;
+
+    if (n_ins > 0) {
+      // this workgroup owns tiles t = b (mod G); copy the survivors that land
+      // there -- now, or during the next iteration's NN scan when this
+      // workgroup runs that iteration on the same tiles of the same round
+      // and has at most one new slot per thread
+      const int t_lo = n0 / TILE, t_hi = (n1 - 1) / TILE;
+      const int t_first = t_lo + ((b - t_lo % G) % G + G) % G;
+      const int n_my = t_first <= t_hi ? (t_hi - t_first) / G + 1 : 0;
+      const bool defer = n_my * TILE <= NT && end == END_NONE &&
+                         !(a.max_iters > 0 && it_done + 1 >= a.max_iters) &&
+                         (!TIERED || tier_grid(n1) == G);
+      if (defer) {
+        if (n_my > 0) {
+          pend_n0 = n0;
+          pend_n1 = n1;
+          pend_trace = trace;
+        }
+      } else {
+        for (int idx = tid; idx < n_my * TILE; idx += NT) {
+          const int s = (t_first + (idx / TILE) * G) * TILE + (idx % TILE);
+          if (s >= n0 && s < n1) {
+            const int r = s - n0;
+            int lo = 0, hi = GR - 1;
+            while (lo < hi) {
+              const int mid = (lo + hi + 1) >> 1;
+              if (s_off[mid] <= r) lo = mid; else hi = mid - 1;
+            }
+            const int e = lo * CPB + (r - s_off[lo]);
+#pragma unroll
+            for (int c = 0; c < D; ++c) a.states[(size_t)c * NC + s] = stg_x[(size_t)c * S + e];
+#pragma unroll
+            for (int c = 0; c < M; ++c) a.actions[(size_t)c * NC + s] = stg_u[(size_t)c * S + e];
+            a.parents[s] = stg_par[e];
+            a.costs[s] = stg_c[e];
+            if (trace != nullptr) {
+              TraceView tv(trace, K, B, D, M);
+              tv.slots[stg_j[e]] = s;
+            }
+          }
+        }
+      }
+    }
 
     if (b == 0 && tid == 0) {
       bk.c_exp += (unsigned long long)B;
