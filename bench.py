@@ -535,7 +535,7 @@ def main():
     ap.add_argument("--c2-seeds", type=int, default=100)
     ap.add_argument("--c3-seeds", type=int, default=100)
     ap.add_argument("--c3-budget-ms", type=float, default=200.0)
-    ap.add_argument("--c4-seeds", type=int, default=50)
+    ap.add_argument("--c4-seeds", type=int, default=100)
     ap.add_argument("--c4-budget-ms", type=float, default=500.0)
     ap.add_argument("--saturating-iters", type=int, default=50)
     ap.add_argument("--refine-budget-ms", type=float, default=500.0)
